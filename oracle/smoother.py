@@ -1,0 +1,239 @@
+"""Multiplicative vertex-patch smoother (oracle, explicit dense local solves).
+
+Definitions followed (Sections 2.1 and 3):
+
+* local solver (eq:main:2): P_j v = Pi_j^T B_j Pi_j A v with B_j = A_j^{-1}
+  (exact) or an approximation of it (the text after eq:main:2 allows that);
+* smoother (eq:s-ell): the product over patches of (I - P_j), applied to the
+  error, i.e. u <- u + Pi_j^T B_j Pi_j (b - A u) patch after patch;
+* colored form (eq:colorized): within one color the patches have disjoint
+  interiors and do not read each other's writes, so the color may be done as
+  one global residual followed by all its patch solves (Algorithm 3).
+
+``sweep_alg3`` is the oracle of a sweep; ``sweep_alg1`` (global residual per
+patch, Algorithm 1) and ``sweep_alg2`` (local residual from the patch's own
+element matrices, Algorithm 2) exist for the order-equivalence pins on tiny
+meshes.  Patch order: colors ascending for a forward sweep, descending for a
+reverse sweep; inside a color the order is irrelevant.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from .assemble import element_matrix, kron_list
+from .fe import assembled_1d
+from .mesh import (patch_vertices, vertex_color, patch_interior, patch_closure,
+                   patch_cells, cell_flat, colors_in_order)
+
+
+class Patches:
+    """All vertex patches of one level with their colors and index sets."""
+
+    def __init__(self, dim: int, k: int, n_cells: int):
+        self.dim, self.k, self.n_cells = dim, k, n_cells
+        self.verts = patch_vertices(dim, n_cells)
+        self.colors = [vertex_color(v) for v in self.verts]
+        self.interior = [patch_interior(dim, k, n_cells, v) for v in self.verts]
+        self.by_color = {c: [] for c in range(2 ** dim)}
+        for j, c in enumerate(self.colors):
+            self.by_color[c].append(j)
+
+    def __len__(self):
+        return len(self.verts)
+
+    def cells(self, j):
+        return [cell_flat(self.dim, self.n_cells, c) for c in patch_cells(self.dim, self.verts[j])]
+
+
+def patch_1d_matrices(k: int, h: float):
+    """Interior blocks M_j, K_j (q x q, q = 2k-1) of the 2-cell 1D patch matrices."""
+    M, K = assembled_1d(k, 2, h)
+    return M[1:-1, 1:-1], K[1:-1, 1:-1]
+
+
+def fdm_factors(dim: int, k: int, h: float):
+    """S = T (x) ... (x) T and Lambda of the fast diagonalization (Appendix A.3).
+
+    T solves the generalized eigenproblem K_j T = M_j T diag(lam) with
+    T^T M_j T = I (SciPy's symmetric-definite solver), so that
+    A_b = S^{-T} diag(Lambda) S^{-1} and A_b^{-1} = S diag(1/Lambda) S^T,
+    Lambda_m = sum_e lam_{m_e}  (m lexicographic, x fastest).
+    """
+    Mj, Kj = patch_1d_matrices(k, h)
+    lam, T = sla.eigh(Kj, Mj)
+    S = kron_list([T] * dim)
+    q = lam.size
+    L = np.zeros((q,) * dim)
+    for e in range(dim):
+        shape = [1] * dim
+        shape[dim - 1 - e] = q
+        L = L + lam.reshape(shape)
+    return S, L.reshape(-1), T, lam
+
+
+def patch_matrix_const(dim: int, k: int, h: float) -> np.ndarray:
+    """A_b = sum_e (x)(K_j at e, M_j elsewhere): constant-coefficient patch matrix."""
+    Mj, Kj = patch_1d_matrices(k, h)
+    A = np.zeros(((2 * k - 1) ** dim,) * 2)
+    for e in range(dim):
+        A += kron_list([Kj if ep == e else Mj for ep in range(dim)])
+    return A
+
+
+def patch_closure_operator(dim: int, k: int, h: float, rho_cells=None) -> np.ndarray:
+    """Local operator on the patch closure, sum over its 2^d cells of rho_c * E.
+
+    Rows and columns are the (2k+1)^d closure nodes, x fastest; the cells are
+    in lexicographic order (x fastest), matching ``Patches.cells``.
+    """
+    p = 2 * k + 1
+    E = element_matrix(dim, k, h)
+    m = (k + 1) ** dim
+    Abar = np.zeros((p ** dim, p ** dim))
+    ncell = 2 ** dim
+    rho = np.ones(ncell) if rho_cells is None else np.asarray(rho_cells, dtype=np.float64)
+    for ci in range(ncell):
+        off = [(ci >> e) & 1 for e in range(dim)]
+        loc = np.zeros(m, dtype=np.int64)
+        for li in range(m):
+            rem = li
+            g = 0
+            stride = 1
+            for e in range(dim):
+                le = rem % (k + 1)
+                rem //= (k + 1)
+                g += (k * off[e] + le) * stride
+                stride *= p
+            loc[li] = g
+        Abar[np.ix_(loc, loc)] += rho[ci] * E
+    return Abar
+
+
+def closure_interior_positions(dim: int, k: int) -> np.ndarray:
+    """Positions of the interior nodes inside the closure numbering."""
+    p = 2 * k + 1
+    out = []
+    for flat in range(p ** dim):
+        rem = flat
+        ok = True
+        for _ in range(dim):
+            a = rem % p
+            rem //= p
+            if a == 0 or a == p - 1:
+                ok = False
+        if ok:
+            out.append(flat)
+    return np.array(out, dtype=np.int64)
+
+
+class LocalSolvers:
+    """The local solvers B_j of one level.
+
+    mode 'exact'   : B_j = (A[I_j, I_j])^{-1}, one dense Cholesky per patch
+    mode 'shared'  : constant coefficient; all A[I_j, I_j] are equal (checked on
+                     a sample) and one factor is used
+    mode 'mean'    : B_j = (rhobar_j * A_b)^{-1}, A_b the rho=1 patch matrix
+    mode 'learned' : B_j = S diag(c_j / (rhobar_j Lambda)) S^T, c_j per patch
+    """
+
+    def __init__(self, A, patches: Patches, mode: str = "exact", rho=None,
+                 scaling=None, check_samples: int = 20):
+        self.mode = mode
+        self.patches = patches
+        dim, k, n = patches.dim, patches.k, patches.n_cells
+        h = 1.0 / n
+        self.factors = None
+        if mode == "exact":
+            self.factors = []
+            for I in patches.interior:
+                Aj = A[I][:, I].toarray()
+                self.factors.append(sla.cho_factor(Aj))
+        elif mode == "shared":
+            Ab = patch_matrix_const(dim, k, h)
+            step = max(1, len(patches) // max(1, check_samples))
+            for j in range(0, len(patches), step):
+                I = patches.interior[j]
+                Aj = A[I][:, I].toarray()
+                if not np.allclose(Aj, Ab, rtol=1e-13, atol=1e-13 * np.abs(Ab).max()):
+                    raise ValueError("patch matrices differ; use mode='exact'")
+            self.shared = sla.cho_factor(Ab)
+        elif mode in ("mean", "learned"):
+            rho = np.asarray(rho, dtype=np.float64).reshape(-1)
+            self.rhobar = np.array([rho[patches.cells(j)].mean() for j in range(len(patches))])
+            if mode == "mean":
+                self.shared = sla.cho_factor(patch_matrix_const(dim, k, h))
+            else:
+                self.S, self.Lam, _, _ = fdm_factors(dim, k, h)
+                self.scaling = np.asarray(scaling, dtype=np.float64).reshape(len(patches), -1)
+        else:
+            raise ValueError(mode)
+
+    def apply(self, j: int, r: np.ndarray) -> np.ndarray:
+        if self.mode == "exact":
+            return sla.cho_solve(self.factors[j], r)
+        if self.mode == "shared":
+            return sla.cho_solve(self.shared, r)
+        if self.mode == "mean":
+            return sla.cho_solve(self.shared, r) / self.rhobar[j]
+        s = self.scaling[j] / (self.rhobar[j] * self.Lam)
+        return self.S @ (s * (self.S.T @ r))
+
+
+def apply_color(A, b, u, patches: Patches, solvers: LocalSolvers, color: int) -> np.ndarray:
+    """One color of the colored smoother: global residual, then all patch solves."""
+    u = np.array(u, dtype=np.float64, copy=True)
+    r = b - A @ u
+    for j in patches.by_color[color]:
+        I = patches.interior[j]
+        u[I] += solvers.apply(j, r[I])
+    return u
+
+
+def sweep_alg3(A, b, u, patches: Patches, solvers: LocalSolvers, reverse: bool = False) -> np.ndarray:
+    """Separated, colorized smoother (Algorithm 3): one sweep over all colors."""
+    for c in colors_in_order(patches.dim, reverse):
+        u = apply_color(A, b, u, patches, solvers, c)
+    return u
+
+
+def sweep_alg1(A, b, u, patches: Patches, solvers: LocalSolvers, reverse: bool = False) -> np.ndarray:
+    """Algorithm 1: the global residual recomputed before every patch (tiny meshes)."""
+    u = np.array(u, dtype=np.float64, copy=True)
+    for c in colors_in_order(patches.dim, reverse):
+        for j in patches.by_color[c]:
+            r = b - A @ u
+            I = patches.interior[j]
+            u[I] += solvers.apply(j, r[I])
+    return u
+
+
+def sweep_alg2(b, u, patches: Patches, rho=None, reverse: bool = False) -> np.ndarray:
+    """Algorithm 2: gather, local residual from the patch's cells, exact local solve, scatter.
+
+    Uses only the patch's element matrices (no global matrix): the local
+    residual is b_j - (Abar_j ubar_j) restricted to the interior rows
+    (eq:main:4), the solve uses the interior block of the same local operator.
+    """
+    dim, k, n = patches.dim, patches.k, patches.n_cells
+    h = 1.0 / n
+    u = np.array(u, dtype=np.float64, copy=True)
+    inner = closure_interior_positions(dim, k)
+    rho_flat = None if rho is None else np.asarray(rho, dtype=np.float64).reshape(-1)
+    const_op = None
+    for c in colors_in_order(dim, reverse):
+        for j in patches.by_color[c]:
+            v = patches.verts[j]
+            if rho_flat is None:
+                if const_op is None:
+                    const_op = patch_closure_operator(dim, k, h)
+                Abar = const_op
+            else:
+                Abar = patch_closure_operator(dim, k, h, rho_flat[patches.cells(j)])
+            clo = patch_closure(dim, k, n, v)
+            I = patch_interior(dim, k, n, v)
+            ubar = u[clo]
+            r = b[I] - Abar[inner] @ ubar
+            d = np.linalg.solve(Abar[np.ix_(inner, inner)], r)
+            u[I] += d
+    return u
