@@ -1,0 +1,247 @@
+/*
+ * vps.h -- C ABI of the MI355X vertex-patch multigrid library (libvps.so).
+ *
+ * Method: Wichrowski, Munch, Kronbichler, Kanschat, "Smoothers with localized
+ * residual computations for geometric multigrid methods" (arXiv 2407.02100).
+ * The library solves A u = b (Section 2, eq:matrix) for the Q_k Laplacian
+ * -div(rho grad u) = f on [0,1]^d, d in {2,3}, homogeneous Dirichlet data
+ * (Appendix A.2), uniform Cartesian meshes with N cells per direction, by CG
+ * preconditioned with a geometric-multigrid V-cycle whose smoother is the
+ * multiplicative vertex-patch smoother (Section 2.1, eq:s-ell) in its
+ * combined, colorized form (Section 3.2, Algorithm 4): per color, every patch
+ * gathers its closure, computes its local residual (eq:main:4), applies the
+ * fast-diagonalization inverse (Appendix A.3, eq:fdm:inverse) and scatters the
+ * update of its interior (eq:scatter).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Vectors.  A level with N_l cells per direction stores the full nodal grid of
+ *   n_l = (k*N_l + 1)^d values, x fastest (index = ix + n1*iy + n1^2*iz).
+ *   Node positions inside a cell are the Gauss-Lobatto points of degree k.
+ *   Dirichlet entries (any ix, iy, iz equal to 0 or n1-1) of inputs must be
+ *   0; the library writes 0 to Dirichlet entries of every vector it outputs.
+ * Memory.  Every vector pointer is a DEVICE pointer owned by the caller; the
+ *   library never frees it.  Work vectors, level constants and the coarse
+ *   solver belong to the context and are freed by vps_destroy.
+ * Levels.  Level 0 is the coarsest (N_0 = N / 2^(n_levels-1) cells), level
+ *   n_levels-1 the finest (N cells).
+ * Patches.  One patch per interior vertex v in [1, N_l-1]^d, numbered
+ *   lexicographically (x fastest).  Color of a patch: sum_e (v_e mod 2) 2^e.
+ *   A patch has (2k+1)^d closure nodes and q^d = (2k-1)^d interior nodes.
+ * Streams.  Every call enqueues its work on the context's HIP stream (given at
+ *   creation, 0 = the null stream) and returns without synchronising, except
+ *   vps_solve, vps_vcycle_iterate, vps_mlp_infer_patches and vps_sync, which
+ *   synchronise.  Errors of asynchronous work surface at the next
+ *   synchronising call.
+ * Errors.  Argument errors are detected on the host before any work is
+ *   enqueued; they return a negative vps_status and set the context's
+ *   message (vps_last_error).  A context is not thread-safe.
+ */
+#ifndef VPS_H
+#define VPS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vps_context vps_context;
+
+typedef enum {
+  VPS_OK = 0,
+  VPS_E_ARG = -1,           /* invalid argument (null pointer, bad level, ...) */
+  VPS_E_UNSUPPORTED = -2,   /* valid but unsupported configuration */
+  VPS_E_HIP = -3,           /* a HIP runtime call failed */
+  VPS_E_NOMEM = -4,         /* device allocation failed */
+  VPS_E_NOT_CONVERGED = -5, /* solver hit maxit before the tolerance */
+  VPS_E_NONFINITE = -6,     /* NaN or Inf met in a solver scalar */
+  VPS_E_STATE = -7          /* call not valid in the context's current state */
+} vps_status;
+
+typedef enum { VPS_F64 = 0, VPS_F32 = 1 } vps_dtype;
+
+typedef enum {
+  VPS_COEF_CONST = 0,          /* rho = 1: exact FDM local solver */
+  VPS_COEF_CELL_MEAN_FDM = 1,  /* rho per cell: residual with rho, FDM with patch mean of rho */
+  VPS_COEF_CELL_LEARNED = 2    /* as 1, each FDM eigenmode scaled by a per-patch factor */
+} vps_coef;
+
+typedef struct {
+  int dim;               /* 2 or 3 */
+  int degree;            /* k, 1..4 */
+  int n_cells;           /* N on the finest level; divisible by 2^(n_levels-1) */
+  int n_levels;          /* >= 1; coarsest level must have >= 2 cells per direction */
+  int pre_sweeps;        /* forward sweeps before the coarse correction, >= 0 */
+  int post_sweeps;       /* reverse sweeps after it, >= 0 */
+  int vcycle_dtype;      /* vps_dtype of everything inside the V-cycle */
+  int coef;              /* vps_coef */
+  int patches_per_block; /* patches along x per workgroup, 0 = automatic */
+} vps_config;
+
+typedef struct {
+  int iterations;           /* CG iterations done */
+  double rel_residual_true; /* ||b - A u||_2 / ||b||_2 over all nodes, FP64 */
+  double seconds;           /* wall time of the solve measured with HIP events */
+  long long fallback_patches; /* patches whose learned scaling fell back to 1 */
+} vps_solve_info;
+
+/* ---- set-up (paper: the mesh hierarchy and the level spaces, Section 2) ---- */
+
+/* Create a context: validates cfg, builds the level constants (1D Q_k mass and
+ * stiffness matrices, the FDM factors of the patch interior, the transfer
+ * matrices, the coarse solver) on the host in FP64 and uploads them, and
+ * allocates the V-cycle work vectors of every level in cfg->vcycle_dtype.
+ * hip_stream: a hipStream_t (may be NULL for the null stream).
+ * Returns VPS_E_UNSUPPORTED for degree outside 1..4, dim outside {2,3},
+ * N not divisible by 2^(n_levels-1) or a coarsest level below 2 cells.
+ * A context whose coarsest grid is too large for the coarse solver (rho = 1:
+ * more than 15 free nodes per direction in 3D, 63 in 2D; cell coefficient:
+ * more than 4096 free nodes) is still created: its smoother, operator and
+ * transfers work, and the calls that need the coarse solver return
+ * VPS_E_UNSUPPORTED. */
+vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out);
+
+/* Free the context and everything it owns.  NULL is accepted. */
+vps_status vps_destroy(vps_context* ctx);
+
+/* Replace the stream all later calls enqueue on. */
+vps_status vps_set_stream(vps_context* ctx, void* hip_stream);
+
+/* Nodes (k N_l + 1)^d of a level, or 0 for an invalid level. */
+size_t vps_level_nodes(const vps_context* ctx, int level);
+
+/* Cells per direction N_l of a level, or 0 for an invalid level. */
+int vps_level_cells(const vps_context* ctx, int level);
+
+/* Number of patches (N_l - 1)^d of a level, or 0 for an invalid level. */
+long long vps_level_patches(const vps_context* ctx, int level);
+
+/* Per-cell coefficient rho on the finest level: N^d FP64 values on the
+ * device, cells lexicographic (x fastest), all > 0.  Coarser levels get the
+ * mean of the 2^d children.  Only for coef != VPS_COEF_CONST.  Rebuilds the
+ * dense coarse solver (host FP64 Cholesky inverse of the coarsest operator,
+ * at most 4096 free nodes).  Synchronises. */
+vps_status vps_set_coefficient(vps_context* ctx, const double* rho_cells_dev);
+
+/* Learned per-patch, per-eigenmode scaling of one level: n_patches(level) x q^d
+ * FP32 values on the device (patch-major; mode index lexicographic over the
+ * 1D eigenvector indices, x fastest) copied into the context; NULL resets to 1.
+ * Only for coef == VPS_COEF_CELL_LEARNED. */
+vps_status vps_set_patch_scaling(vps_context* ctx, int level, const float* c_dev);
+
+/* ---- level operators ---- */
+
+/* Au = A_l u, matrix-free (sum factorisation over cell tiles). */
+vps_status vps_apply(vps_context* ctx, int level, const void* u, void* Au, vps_dtype t);
+
+/* r = b - A_l u. */
+vps_status vps_residual(vps_context* ctx, int level, const void* b, const void* u, void* r,
+                        vps_dtype t);
+
+/* Restriction (the transpose of the prolongation, Section 2):
+ * r_coarse = P^T r_fine from level fine_level to fine_level-1. */
+vps_status vps_restrict(vps_context* ctx, int fine_level, const void* r_fine, void* r_coarse,
+                        vps_dtype t);
+
+/* Prolongation (embedding of the coarse FE space, Section 2):
+ * u_fine += P e_coarse from level fine_level-1 to fine_level. */
+vps_status vps_prolongate_add(vps_context* ctx, int fine_level, const void* e_coarse,
+                              void* u_fine, vps_dtype t);
+
+/* x = A_0^{-1} b on the coarsest level: fast diagonalization of the whole
+ * coarse grid for rho = 1, dense explicit inverse otherwise. */
+vps_status vps_coarse_solve(vps_context* ctx, const void* b, void* x, vps_dtype t);
+
+/* ---- the smoother (Algorithm 4, combined and colorized) ---- */
+
+/* One color of the smoother on a level, in place on u: every patch of the
+ * color computes r_j = b_j - Abar_j ubar_j and u_j += B_j r_j.  color in
+ * [0, 2^d).  u and b: level vectors of dtype t. */
+vps_status vps_smooth_color(vps_context* ctx, int level, void* u, const void* b, vps_dtype t,
+                            int color);
+
+/* `sweeps` sweeps of the smoother on a level, in place on u.  A sweep runs the
+ * colors 0..2^d-1 (reverse = 0) or 2^d-1..0 (reverse != 0), one launch each. */
+vps_status vps_smooth(vps_context* ctx, int level, void* u, const void* b, vps_dtype t,
+                      int sweeps, int reverse);
+
+/* ---- multigrid and the outer solver ---- */
+
+/* z = V r: one V-cycle on the finest level from a zero initial guess,
+ * pre_sweeps forward sweeps, coarse correction, post_sweeps reverse sweeps,
+ * computed in cfg->vcycle_dtype (FP64 r and z are converted at the ends). */
+vps_status vps_vcycle(vps_context* ctx, const double* r, double* z);
+
+/* Solve A u = b (finest level) from u = 0 by CG preconditioned with the
+ * V-cycle (flexible CG when the V-cycle runs in FP32), all Krylov vectors,
+ * dot products and updates in FP64, until ||b - A u|| <= rtol ||b|| with the
+ * true residual recomputed at the end.  Synchronises.  info may be NULL.
+ * Returns VPS_E_NOT_CONVERGED after maxit iterations (u holds the iterate),
+ * VPS_E_NONFINITE if a CG scalar is NaN/Inf. */
+vps_status vps_solve(vps_context* ctx, const double* b, double* u, double rtol, int maxit,
+                     vps_solve_info* info);
+
+/* Stationary iteration u <- u + V(b - A u), `iters` times, starting from the
+ * given u (FP64, device).  res_hist (host, iters+1 doubles, may be NULL)
+ * receives ||b - A u||_2 before the first and after every iteration.
+ * Synchronises. */
+vps_status vps_vcycle_iterate(vps_context* ctx, const double* b, double* u, int iters,
+                              double* res_hist);
+
+/* ---- learned eigenmode scaling (variable coefficient, d = 3) ---- */
+
+/* Features of every patch of a level: x[j][c] = log(rho_c / rhobar_j) over the
+ * patch's 2^d cells (lexicographic, x fastest), FP32, n_patches x 2^d. */
+vps_status vps_patch_features(vps_context* ctx, int level, float* x_dev);
+
+/* Training targets from exact dense patch operators.  rho8: n x 2^d FP64
+ * per-cell coefficients of n patches (device).  Per patch: assemble
+ * A_j(rho), Y = S^T A_j S, solve (Y o Y) d = diag(Y) by Cholesky,
+ * c*_m = rhobar Lambda_m d_m.  cstar: n x q^d FP64 (device). */
+vps_status vps_patch_targets(vps_context* ctx, const double* rho8_dev, long long n,
+                             double* cstar_dev);
+
+/* MLP n_in -> n_h (tanh) -> n_h (tanh) -> n_out with n_in = 2^d, n_h = 64,
+ * n_out = q^d, FP32.  params: flat W1 (n_h x n_in, row-major), b1, W2, b2, W3
+ * (n_out x n_h), b3.  x: n x n_in.  y: n x n_out.  act_cache (may be NULL):
+ * n x 2 n_h, the two hidden activations, needed by vps_mlp_backward. */
+vps_status vps_mlp_forward(vps_context* ctx, const float* params, const float* x, long long n,
+                           float* y, float* act_cache);
+
+/* dy = d(loss)/dy for loss = mean over n x n_out of (y - t)^2; loss_out
+ * (device, 1 float, may be NULL) receives the loss. */
+vps_status vps_mlp_loss_grad(vps_context* ctx, const float* y, const float* t, long long n,
+                             float* dy, float* loss_out);
+
+/* dparams = gradient of sum(dy * y) w.r.t. params (overwritten). */
+vps_status vps_mlp_backward(vps_context* ctx, const float* params, const float* x,
+                            const float* act_cache, const float* dy, long long n,
+                            float* dparams);
+
+/* One Adam step (step counts from 1) on params with moments m, v. */
+vps_status vps_mlp_adam(vps_context* ctx, float* params, const float* dparams, float* m,
+                        float* v, int step, float lr, float b1, float b2, float eps);
+
+/* Run the MLP on every patch of a level and store c = clamp(exp(y), 1/4, 4) as
+ * the level's scaling; patches with non-finite outputs fall back to c = 1.
+ * fallback (host, may be NULL) receives their number.  Synchronises. */
+vps_status vps_mlp_infer_patches(vps_context* ctx, int level, const float* params,
+                                 long long* fallback);
+
+/* ---- misc ---- */
+
+/* Wait for the context's stream; reports asynchronous HIP errors. */
+vps_status vps_sync(vps_context* ctx);
+
+/* Static description of a status code. */
+const char* vps_status_string(vps_status s);
+
+/* Message of the last error on this context ("" if none); valid until the next call. */
+const char* vps_last_error(const vps_context* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VPS_H */

@@ -1,0 +1,109 @@
+// Host-side launchers of libvps kernels (library-internal).
+//
+// Each launcher takes runtime descriptions (device pointers, sizes, and the
+// level's 1D matrices as host FP64 arrays), builds the kernel's argument
+// struct in the kernel's arithmetic type and launches on the given stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace vps {
+
+// Tile sizes (cells per direction) of the operator and transfer kernels.
+constexpr int op_tc(int K, int D) { return D == 2 ? (K <= 2 ? 4 : 2) : (K == 1 ? 8 : (K == 2 ? 4 : 2)); }
+constexpr int restrict_tc(int K, int D) { return D == 2 ? 2 : (K <= 2 ? 2 : 1); }
+constexpr int prolong_tc(int K, int D) { return D == 2 ? 2 : (K <= 2 ? 2 : 1); }
+
+// Patches per workgroup along x that the automatic choice uses.
+int default_patches_per_block(int K, int D, int coef, bool fp64);
+// Supported explicit choices.
+bool valid_patches_per_block(int pb);
+
+struct PatchLaunch {
+  void* u;
+  const void* b;
+  const void* rho;     // per-cell coefficient of the level (same dtype as u), coef != 0
+  const float* scal;   // per-patch eigenmode factors, coef == 2
+  int n1, ncell;
+  int color;           // bit e = parity of the vertex index along direction e
+  int coef;            // 0, 1, 2
+  int pb;              // patches per workgroup along x
+  const double* M[2];  // Q x P each (see PatchMats)
+  const double* Kst[2];
+  const double* T1;    // Q x Q
+  const double* lam;   // Q
+};
+
+template <typename T, int K, int D>
+hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s);
+
+struct TileLaunch {
+  const void* in;
+  const void* b;   // operator only: r = b - A u when non-null
+  void* out;
+  int n1_in, n1_out;
+  int tiles;       // tiles per direction
+  const double* G0;  // NO x NI
+  const double* G1;  // NO x NI (operator stiffness) or null
+};
+
+template <typename T, int K, int D>
+hipError_t launch_operator(const TileLaunch& L, hipStream_t s);
+template <typename T, int K, int D>
+hipError_t launch_restrict(const TileLaunch& L, hipStream_t s);
+template <typename T, int K, int D>
+hipError_t launch_prolong(const TileLaunch& L, hipStream_t s);
+
+// Variable-coefficient operator (one thread per node, sum over the node's cells).
+struct VarOpLaunch {
+  const void* u;
+  const void* b;
+  void* out;
+  const void* rho;
+  int n1, ncell;
+  const double* Mc;  // (K+1)^2 cell mass  (h-scaled)
+  const double* Kc;  // (K+1)^2 cell stiffness (h-scaled)
+};
+template <typename T, int K, int D>
+hipError_t launch_operator_var(const VarOpLaunch& L, hipStream_t s);
+
+// Coarse solvers.
+struct CoarseFdmLaunch {
+  const void* b;
+  void* x;
+  int n0;           // free nodes per direction
+  const void* T0;   // n0 x n0, device, in the kernel's type
+  const void* lam0; // n0, device, in the kernel's type
+};
+template <typename T, int D>
+hipError_t launch_coarse_fdm(const CoarseFdmLaunch& L, hipStream_t s);
+constexpr int coarse_fdm_max_n0(int D) { return D == 3 ? 15 : 63; }
+
+template <typename T>
+hipError_t launch_coarse_dense(const void* Ainv, const int* free_idx, int nfree, const void* b, void* x,
+                               size_t nodes, hipStream_t s);
+
+// Vector kernels.
+template <typename T>
+hipError_t launch_fill(void* x, double v, size_t n, hipStream_t s);
+template <typename Ti, typename To>
+hipError_t launch_cast(const void* in, void* out, size_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_axpy(double a, const void* x, void* y, size_t n, hipStream_t s);  // y += a x
+hipError_t launch_xpay(const double* x, double a, double* y, size_t n, hipStream_t s);  // y = x + a y
+// x += alpha p; r -= alpha q; partial sums of r.r into partial[0..nblk)
+hipError_t launch_cg_update(double alpha, const double* p, const double* q, double* x, double* r, size_t n,
+                            double* partial, int* nblk, hipStream_t s);
+// partial sums of (x.y) into partial[0..nblk) and, if x2/y2 are given, (x2.y2) into partial[nblk..2 nblk)
+hipError_t launch_dot_partial(const double* x, const double* y, const double* x2, const double* y2, size_t n,
+                              double* partial, int* nblk, hipStream_t s);
+// out[j] = sum of partial[j*nblk .. (j+1)*nblk), j < ndot
+hipError_t launch_dot_final(const double* partial, int nblk, int ndot, double* out, hipStream_t s);
+constexpr int kDotBlocks = 1024;
+
+// Per-cell coefficient of the next coarser level: mean of the 2^D children.
+hipError_t launch_coarsen_rho(const double* fine, double* coarse, int ncell_coarse, int D, hipStream_t s);
+
+}  // namespace vps

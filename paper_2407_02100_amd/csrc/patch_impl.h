@@ -1,0 +1,75 @@
+// Launcher of the patch smoother kernel for one degree (VPS_PATCH_K), included
+// by patch_k<K>.hip so that the degrees compile in parallel.
+#include "kernels.h"
+#include "launch.h"
+
+namespace vps {
+
+namespace {
+
+template <typename T, int K, int D, int COEF, int PB>
+hipError_t go_patch(const PatchArgs<T, K>& a, hipStream_t s) {
+  using Sh = PatchKernelShape<T, K, D, COEF, PB>;
+  if constexpr (Sh::LDS_BYTES + 4096 > 65536) {
+    return hipErrorInvalidValue;  // shape does not fit the 64 KiB workgroup LDS limit
+  } else {
+    dim3 grid((a.np[0] + PB - 1) / PB, a.np[1], D == 3 ? a.np[2] : 1);
+    patch_color_kernel<T, K, D, COEF, PB><<<grid, kBlock, 0, s>>>(a);
+    return hipGetLastError();
+  }
+}
+
+template <typename T, int K, int D, int COEF>
+hipError_t go_patch_pb(const PatchArgs<T, K>& a, int pb, hipStream_t s) {
+  switch (pb) {
+    case 1: return go_patch<T, K, D, COEF, 1>(a, s);
+    case 2: return go_patch<T, K, D, COEF, 2>(a, s);
+    case 4: return go_patch<T, K, D, COEF, 4>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+template <typename T, int K, int D>
+hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
+  static_assert(sizeof(PatchArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
+  using PM = PatchMats<T, K>;
+  constexpr int P = PM::P, Q = PM::Q;
+  PatchArgs<T, K> a;
+  a.u = (T*)L.u;
+  a.b = (const T*)L.b;
+  a.rho = (const T*)L.rho;
+  a.scal = L.scal;
+  a.n1 = L.n1;
+  a.ncell = L.ncell;
+  const int N = L.ncell;
+  for (int e = 0; e < 3; ++e) {
+    if (e >= D) { a.v0[e] = 1; a.np[e] = 1; continue; }
+    const int bit = (L.color >> e) & 1;
+    const int v0 = bit ? 1 : 2;
+    a.v0[e] = v0;
+    a.np[e] = (v0 <= N - 1) ? (N - 1 - v0) / 2 + 1 : 0;
+    if (a.np[e] == 0) return hipSuccess;  // no patch of this color
+  }
+  for (int h = 0; h < 2; ++h)
+    for (int i = 0; i < Q * P; ++i) {
+      a.m.M[h][i] = L.M[h] ? (T)L.M[h][i] : T(0);
+      a.m.Kst[h][i] = L.Kst[h] ? (T)L.Kst[h][i] : T(0);
+    }
+  for (int i = 0; i < Q * Q; ++i) a.m.T1[i] = (T)L.T1[i];
+  for (int i = 0; i < Q; ++i) a.m.lam[i] = (T)L.lam[i];
+  switch (L.coef) {
+    case 0: return go_patch_pb<T, K, D, 0>(a, L.pb, s);
+    case 1: return go_patch_pb<T, K, D, 1>(a, L.pb, s);
+    case 2: return go_patch_pb<T, K, D, 2>(a, L.pb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_patch_color<double, VPS_PATCH_K, 2>(const PatchLaunch&, hipStream_t);
+template hipError_t launch_patch_color<double, VPS_PATCH_K, 3>(const PatchLaunch&, hipStream_t);
+template hipError_t launch_patch_color<float, VPS_PATCH_K, 2>(const PatchLaunch&, hipStream_t);
+template hipError_t launch_patch_color<float, VPS_PATCH_K, 3>(const PatchLaunch&, hipStream_t);
+
+}  // namespace vps

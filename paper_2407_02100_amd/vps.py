@@ -1,0 +1,293 @@
+"""Thin ctypes binding of libvps (the C ABI declared in include/vps.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Torch tensors supply device memory (``data_ptr``) and the HIP
+stream (``torch.cuda.current_stream().cuda_stream``).  The module-level
+functions carry the C names; :class:`Context` wraps a ``vps_context*``.
+
+Loading fails loudly (``VpsError``) when ``libvps.so`` has not been built;
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvps.so")
+
+VPS_OK, VPS_E_ARG, VPS_E_UNSUPPORTED, VPS_E_HIP = 0, -1, -2, -3
+VPS_E_NOMEM, VPS_E_NOT_CONVERGED, VPS_E_NONFINITE, VPS_E_STATE = -4, -5, -6, -7
+VPS_F64, VPS_F32 = 0, 1
+VPS_COEF_CONST, VPS_COEF_CELL_MEAN_FDM, VPS_COEF_CELL_LEARNED = 0, 1, 2
+
+_COEF = {"const": VPS_COEF_CONST, "mean": VPS_COEF_CELL_MEAN_FDM, "learned": VPS_COEF_CELL_LEARNED}
+_DTYPE = {"f64": VPS_F64, "f32": VPS_F32}
+
+
+class VpsError(RuntimeError):
+    def __init__(self, status, message=""):
+        self.status = status
+        super().__init__(f"{status_string(status)} ({status}): {message}" if message else status_string(status))
+
+
+class vps_config(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("degree", ctypes.c_int), ("n_cells", ctypes.c_int),
+                ("n_levels", ctypes.c_int), ("pre_sweeps", ctypes.c_int), ("post_sweeps", ctypes.c_int),
+                ("vcycle_dtype", ctypes.c_int), ("coef", ctypes.c_int), ("patches_per_block", ctypes.c_int)]
+
+
+class vps_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("rel_residual_true", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("fallback_patches", ctypes.c_longlong)]
+
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_ll = ctypes.c_longlong
+_d = ctypes.c_double
+_f = ctypes.c_float
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "vps_create": (_i, [ctypes.POINTER(vps_config), _vp, ctypes.POINTER(_vp)]),
+    "vps_destroy": (_i, [_vp]),
+    "vps_set_stream": (_i, [_vp, _vp]),
+    "vps_level_nodes": (ctypes.c_size_t, [_vp, _i]),
+    "vps_level_cells": (_i, [_vp, _i]),
+    "vps_level_patches": (_ll, [_vp, _i]),
+    "vps_set_coefficient": (_i, [_vp, _vp]),
+    "vps_set_patch_scaling": (_i, [_vp, _i, _vp]),
+    "vps_apply": (_i, [_vp, _i, _vp, _vp, _i]),
+    "vps_residual": (_i, [_vp, _i, _vp, _vp, _vp, _i]),
+    "vps_restrict": (_i, [_vp, _i, _vp, _vp, _i]),
+    "vps_prolongate_add": (_i, [_vp, _i, _vp, _vp, _i]),
+    "vps_coarse_solve": (_i, [_vp, _vp, _vp, _i]),
+    "vps_smooth_color": (_i, [_vp, _i, _vp, _vp, _i, _i]),
+    "vps_smooth": (_i, [_vp, _i, _vp, _vp, _i, _i, _i]),
+    "vps_vcycle": (_i, [_vp, _vp, _vp]),
+    "vps_solve": (_i, [_vp, _vp, _vp, _d, _i, ctypes.POINTER(vps_solve_info)]),
+    "vps_vcycle_iterate": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d)]),
+    "vps_patch_features": (_i, [_vp, _i, _vp]),
+    "vps_patch_targets": (_i, [_vp, _vp, _ll, _vp]),
+    "vps_mlp_forward": (_i, [_vp, _vp, _vp, _ll, _vp, _vp]),
+    "vps_mlp_loss_grad": (_i, [_vp, _vp, _vp, _ll, _vp, _vp]),
+    "vps_mlp_backward": (_i, [_vp, _vp, _vp, _vp, _vp, _ll, _vp]),
+    "vps_mlp_adam": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _f, _f, _f, _f]),
+    "vps_mlp_infer_patches": (_i, [_vp, _i, _vp, ctypes.POINTER(_ll)]),
+    "vps_sync": (_i, [_vp]),
+    "vps_status_string": (ctypes.c_char_p, [_i]),
+    "vps_last_error": (ctypes.c_char_p, [_vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libvps.so (raises VpsError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise VpsError(VPS_E_STATE, f"{LIB_PATH} is missing; build it with "
+                                        "`python -m paper_2407_02100_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().vps_status_string(int(s)).decode()
+
+
+def _ptr(t):
+    """Device pointer of a contiguous CUDA tensor (or None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise VpsError(VPS_E_ARG, "tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise VpsError(VPS_E_ARG, "tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_of(t):
+    import torch
+    if t.dtype == torch.float64:
+        return VPS_F64
+    if t.dtype == torch.float32:
+        return VPS_F32
+    raise VpsError(VPS_E_ARG, f"unsupported dtype {t.dtype}")
+
+
+def _current_stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """Owns a vps_context*.  Methods mirror the C entry points (without the prefix)."""
+
+    def __init__(self, dim, degree, n_cells, n_levels, pre=1, post=1, vcycle_dtype="f64",
+                 coef="const", patches_per_block=0, stream=None):
+        cfg = vps_config(dim, degree, n_cells, n_levels, pre, post, _DTYPE[vcycle_dtype], _COEF[coef],
+                         patches_per_block)
+        self.cfg = cfg
+        self.dim, self.degree, self.n_levels = dim, degree, n_levels
+        h = _vp()
+        st = lib().vps_create(ctypes.byref(cfg), stream if stream is not None else _current_stream(),
+                              ctypes.byref(h))
+        if st != VPS_OK:
+            raise VpsError(st, "vps_create")
+        self.h = h
+
+    # -- helpers --
+    def _check(self, st, what):
+        if st != VPS_OK:
+            msg = lib().vps_last_error(self.h).decode() if self.h else ""
+            raise VpsError(st, f"{what}: {msg}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vps_destroy(self.h)
+            self.h = None
+
+    destroy = close
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- queries --
+    def level_nodes(self, level):
+        return int(lib().vps_level_nodes(self.h, level))
+
+    def level_cells(self, level):
+        return int(lib().vps_level_cells(self.h, level))
+
+    def level_patches(self, level):
+        return int(lib().vps_level_patches(self.h, level))
+
+    def set_stream(self, stream):
+        self._check(lib().vps_set_stream(self.h, stream), "vps_set_stream")
+
+    # -- set-up --
+    def set_coefficient(self, rho_cells):
+        self._check(lib().vps_set_coefficient(self.h, _ptr(rho_cells)), "vps_set_coefficient")
+
+    def set_patch_scaling(self, level, c):
+        self._check(lib().vps_set_patch_scaling(self.h, level, _ptr(c)), "vps_set_patch_scaling")
+
+    # -- level operators --
+    def apply(self, level, u, Au):
+        self._check(lib().vps_apply(self.h, level, _ptr(u), _ptr(Au), _dtype_of(u)), "vps_apply")
+
+    def residual(self, level, b, u, r):
+        self._check(lib().vps_residual(self.h, level, _ptr(b), _ptr(u), _ptr(r), _dtype_of(u)), "vps_residual")
+
+    def restrict(self, fine_level, r_fine, r_coarse):
+        self._check(lib().vps_restrict(self.h, fine_level, _ptr(r_fine), _ptr(r_coarse), _dtype_of(r_fine)),
+                    "vps_restrict")
+
+    def prolongate_add(self, fine_level, e_coarse, u_fine):
+        self._check(lib().vps_prolongate_add(self.h, fine_level, _ptr(e_coarse), _ptr(u_fine),
+                                             _dtype_of(u_fine)), "vps_prolongate_add")
+
+    def coarse_solve(self, b, x):
+        self._check(lib().vps_coarse_solve(self.h, _ptr(b), _ptr(x), _dtype_of(b)), "vps_coarse_solve")
+
+    # -- smoother --
+    def smooth_color(self, level, u, b, color):
+        self._check(lib().vps_smooth_color(self.h, level, _ptr(u), _ptr(b), _dtype_of(u), color),
+                    "vps_smooth_color")
+
+    def smooth(self, level, u, b, sweeps=1, reverse=False):
+        self._check(lib().vps_smooth(self.h, level, _ptr(u), _ptr(b), _dtype_of(u), sweeps, int(reverse)),
+                    "vps_smooth")
+
+    # -- multigrid / solver --
+    def vcycle(self, r, z):
+        self._check(lib().vps_vcycle(self.h, _ptr(r), _ptr(z)), "vps_vcycle")
+
+    def solve(self, b, u, rtol=1e-10, maxit=100, check=True):
+        info = vps_solve_info()
+        st = lib().vps_solve(self.h, _ptr(b), _ptr(u), rtol, maxit, ctypes.byref(info))
+        if check:
+            self._check(st, "vps_solve")
+        return {"status": st, "iterations": info.iterations, "rel_residual_true": info.rel_residual_true,
+                "seconds": info.seconds, "fallback_patches": info.fallback_patches}
+
+    def vcycle_iterate(self, b, u, iters):
+        hist = (ctypes.c_double * (iters + 1))()
+        self._check(lib().vps_vcycle_iterate(self.h, _ptr(b), _ptr(u), iters, hist), "vps_vcycle_iterate")
+        return list(hist)
+
+    # -- learned scaling --
+    def patch_features(self, level, x):
+        self._check(lib().vps_patch_features(self.h, level, _ptr(x)), "vps_patch_features")
+
+    def patch_targets(self, rho8, cstar):
+        self._check(lib().vps_patch_targets(self.h, _ptr(rho8), rho8.shape[0], _ptr(cstar)), "vps_patch_targets")
+
+    def mlp_forward(self, params, x, y, act=None):
+        self._check(lib().vps_mlp_forward(self.h, _ptr(params), _ptr(x), x.shape[0], _ptr(y), _ptr(act)),
+                    "vps_mlp_forward")
+
+    def mlp_loss_grad(self, y, t, dy, loss=None):
+        self._check(lib().vps_mlp_loss_grad(self.h, _ptr(y), _ptr(t), y.shape[0], _ptr(dy), _ptr(loss)),
+                    "vps_mlp_loss_grad")
+
+    def mlp_backward(self, params, x, act, dy, dparams):
+        self._check(lib().vps_mlp_backward(self.h, _ptr(params), _ptr(x), _ptr(act), _ptr(dy), x.shape[0],
+                                           _ptr(dparams)), "vps_mlp_backward")
+
+    def mlp_adam(self, params, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self._check(lib().vps_mlp_adam(self.h, _ptr(params), _ptr(g), _ptr(m), _ptr(v), step, lr, b1, b2, eps),
+                    "vps_mlp_adam")
+
+    def mlp_infer_patches(self, level, params):
+        fb = ctypes.c_longlong(0)
+        self._check(lib().vps_mlp_infer_patches(self.h, level, _ptr(params), ctypes.byref(fb)),
+                    "vps_mlp_infer_patches")
+        return int(fb.value)
+
+    def sync(self):
+        self._check(lib().vps_sync(self.h), "vps_sync")
+
+
+def vps_create(*args, **kwargs) -> Context:
+    return Context(*args, **kwargs)
+
+
+def _method_alias(name):
+    def f(ctx, *args, **kwargs):
+        return getattr(ctx, name)(*args, **kwargs)
+    f.__name__ = "vps_" + name
+    f.__doc__ = f"Module-level form of Context.{name} (C entry point vps_{name})."
+    return f
+
+
+for _n in ("destroy", "set_stream", "level_nodes", "level_cells", "level_patches", "set_coefficient",
+           "set_patch_scaling", "apply", "residual", "restrict", "prolongate_add", "coarse_solve",
+           "smooth_color", "smooth", "vcycle", "solve", "vcycle_iterate", "patch_features", "patch_targets",
+           "mlp_forward", "mlp_loss_grad", "mlp_backward", "mlp_adam", "mlp_infer_patches", "sync"):
+    globals()["vps_" + _n] = _method_alias(_n)
+
+
+def vps_status_string(s):
+    return status_string(s)
+
+
+def mlp_param_count(nin, nout, hidden=64):
+    return hidden * nin + hidden + hidden * hidden + hidden + nout * hidden + nout

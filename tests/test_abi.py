@@ -1,0 +1,71 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+and rejects invalid configurations on the host (no GPU work is started)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vps.h")
+LIB = os.path.join(ROOT, "paper_2407_02100_amd", "libvps.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vps_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libvps.so is not built (run python -m paper_2407_02100_amd.build)")
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_every_symbol():
+    from paper_2407_02100_amd import vps
+    for n in declared_functions():
+        assert n in vps.SIGNATURES, n
+
+
+def test_status_strings(lib):
+    from paper_2407_02100_amd import vps
+    assert vps.status_string(0) == "ok"
+    assert vps.status_string(-2) == "unsupported configuration"
+    assert vps.status_string(-99) == "unknown status"
+
+
+@pytest.mark.parametrize("cfg,status", [
+    (dict(dim=4, degree=2, n_cells=8, n_levels=2), -2),
+    (dict(dim=3, degree=5, n_cells=8, n_levels=2), -2),
+    (dict(dim=3, degree=2, n_cells=12, n_levels=4), -2),   # 12 not divisible by 8
+    (dict(dim=3, degree=2, n_cells=8, n_levels=4), -2),    # coarsest level has 1 cell
+    (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_block=3), -2),
+    (dict(dim=2, degree=2, n_cells=8, n_levels=2, pre=-1), -1),
+])
+def test_create_rejects_invalid_configurations(lib, cfg, status):
+    from paper_2407_02100_amd import vps
+    c = vps.vps_config(cfg["dim"], cfg["degree"], cfg["n_cells"], cfg["n_levels"], cfg.get("pre", 1), 1, 0, 0,
+                       cfg.get("patches_per_block", 0))
+    h = ctypes.c_void_p()
+    st = vps.lib().vps_create(ctypes.byref(c), None, ctypes.byref(h))
+    assert st == status
+    assert not h.value
+
+
+def test_null_arguments_are_rejected(lib):
+    from paper_2407_02100_amd import vps
+    L = vps.lib()
+    assert L.vps_create(None, None, None) == -1
+    assert L.vps_destroy(None) == 0
+    assert L.vps_level_nodes(None, 0) == 0
+    assert L.vps_sync(None) == -1

@@ -1,0 +1,158 @@
+"""GPU parity of the variable-coefficient smoother and the learned-scaling kernels."""
+import numpy as np
+import pytest
+
+import vps_inputs as vi
+from oracle import assemble, smoother, learned, mlp, multigrid
+from tests.gpu_util import dev, host, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vps():
+    from paper_2407_02100_amd import vps as m
+    return m
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 9), (3, 2, 7), (3, 1, 6), (3, 3, 5)])
+def test_variable_coefficient_smooth_and_apply(vps, dim, k, N):
+    say("varcoef", dim, k, N)
+    rho = np.exp(np.random.default_rng(dim * 10 + k).standard_normal(N ** dim))
+    A = assemble.assemble(dim, k, N, rho)
+    P = smoother.Patches(dim, k, N)
+    S = smoother.LocalSolvers(A, P, "mean", rho=rho)
+    b = vi.seeded_vector(dim, k, N, 41)
+    u0 = vi.seeded_vector(dim, k, N, 42)
+    import torch
+    with vps.Context(dim, k, N, 1, coef="mean") as ctx:
+        ctx.set_coefficient(dev(rho))
+        out = torch.empty(u0.size, dtype=torch.float64, device="cuda")
+        ctx.apply(0, dev(u0), out)
+        assert rel(host(out), A @ u0) <= 1e-13
+        u = dev(u0)
+        uo = u0
+        for c in range(2 ** dim):
+            ctx.smooth_color(0, u, dev(b), c)
+            uo = smoother.apply_color(A, b, uo, P, S, c)
+            assert rel(host(u), uo) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 9), (3, 2, 7)])
+def test_learned_scaling_smooth(vps, dim, k, N):
+    say("learned smooth", dim, k, N)
+    rng = np.random.default_rng(5)
+    rho = np.exp(rng.standard_normal(N ** dim))
+    q = 2 * k - 1
+    npatch = (N - 1) ** dim
+    scal = rng.uniform(0.5, 2.0, size=(npatch, q ** dim))
+    A = assemble.assemble(dim, k, N, rho)
+    P = smoother.Patches(dim, k, N)
+    S = smoother.LocalSolvers(A, P, "learned", rho=rho, scaling=scal.astype(np.float32).astype(np.float64))
+    b = vi.seeded_vector(dim, k, N, 43)
+    u0 = vi.seeded_vector(dim, k, N, 44)
+    import torch
+    with vps.Context(dim, k, N, 1, coef="learned") as ctx:
+        ctx.set_coefficient(dev(rho))
+        ctx.set_patch_scaling(0, dev(scal, torch.float32))
+        u = dev(u0)
+        ctx.smooth(0, u, dev(b), sweeps=1)
+        want = smoother.sweep_alg3(A, b, u0, P, S)
+        assert rel(host(u), want) <= 1e-12
+
+
+def test_coarse_rho_and_vcycle_variable(vps):
+    dim, k, N, L = 3, 2, 8, 2
+    say("varcoef vcycle", dim, k, N)
+    rho = vi.rho_cells(N, 3, corr_len=0.5, std=0.5)
+    H = multigrid.Hierarchy(dim, k, N, L, rho=rho, mode="mean")
+    r = vi.seeded_vector(dim, k, N, 45)
+    want = H.vcycle(r)
+    import torch
+    with vps.Context(dim, k, N, L, coef="mean") as ctx:
+        ctx.set_coefficient(dev(rho))
+        z = torch.empty(r.size, dtype=torch.float64, device="cuda")
+        ctx.vcycle(dev(r), z)
+        assert rel(host(z), want) <= 1e-11
+
+
+def test_patch_features_and_targets(vps):
+    dim, k, N = 3, 2, 6
+    say("features/targets")
+    rho = np.exp(np.random.default_rng(7).standard_normal(N ** dim))
+    P = smoother.Patches(dim, k, N)
+    import torch
+    with vps.Context(dim, k, N, 1, coef="learned") as ctx:
+        ctx.set_coefficient(dev(rho))
+        x = torch.empty((len(P), 8), dtype=torch.float32, device="cuda")
+        ctx.patch_features(0, x)
+        want = np.array([learned.features(rho[P.cells(j)]) for j in range(len(P))])
+        assert np.abs(host(x) - want).max() <= 1e-6
+        rho8 = np.exp(1.3 * np.random.default_rng(8).standard_normal((64, 8)))
+        cs = torch.empty((64, 27), dtype=torch.float64, device="cuda")
+        ctx.patch_targets(dev(rho8), cs)
+        want = np.array([learned.targets(3, 2, r) for r in rho8])
+        assert rel(host(cs), want) <= 1e-10
+
+
+def test_mlp_forward_backward_adam(vps):
+    say("mlp")
+    import torch
+    rng = np.random.default_rng(9)
+    n = 300
+    p = mlp.init_params(3).astype(np.float32)
+    X = rng.standard_normal((n, 8)).astype(np.float32)
+    T = (0.3 * rng.standard_normal((n, 27))).astype(np.float32)
+    Yo, cache = mlp.forward(p.astype(np.float64), X.astype(np.float64))
+    go = mlp.backward(p.astype(np.float64), cache, mlp.loss_grad(Yo, T.astype(np.float64)))
+    with vps.Context(3, 2, 4, 1, coef="learned") as ctx:
+        pd, xd, td = dev(p, torch.float32), dev(X, torch.float32), dev(T, torch.float32)
+        y = torch.empty((n, 27), dtype=torch.float32, device="cuda")
+        act = torch.empty((n, 128), dtype=torch.float32, device="cuda")
+        ctx.mlp_forward(pd, xd, y, act)
+        assert rel(host(y), Yo) <= 1e-5
+        dy = torch.empty_like(y)
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        ctx.mlp_loss_grad(y, td, dy, loss)
+        assert abs(float(host(loss)[0]) - mlp.loss(Yo, T)) <= 1e-5 * mlp.loss(Yo, T)
+        g = torch.empty_like(pd)
+        ctx.mlp_backward(pd, xd, act, dy, g)
+        assert rel(host(g), go) <= 1e-4
+        m = torch.zeros_like(pd)
+        v = torch.zeros_like(pd)
+        ctx.mlp_adam(pd, g, m, v, 1, lr=1e-3)
+        want, _, _ = mlp.adam_step(p.astype(np.float64), host(g), np.zeros(p.size), np.zeros(p.size), 1, lr=1e-3)
+        assert np.abs(host(pd) - want).max() <= 1e-6
+
+
+def test_infer_patches_and_fallback(vps):
+    dim, k, N = 3, 2, 6
+    say("infer")
+    import torch
+    rng = np.random.default_rng(10)
+    rho = np.exp(rng.standard_normal(N ** dim))
+    p = mlp.init_params(4).astype(np.float32)
+    P = smoother.Patches(dim, k, N)
+    feats = np.array([learned.features(rho[P.cells(j)]) for j in range(len(P))])
+    Y, _ = mlp.forward(p.astype(np.float64), feats.astype(np.float32).astype(np.float64))
+    scal = learned.scaling_from_output(Y)
+    A = assemble.assemble(dim, k, N, rho)
+    S = smoother.LocalSolvers(A, P, "learned", rho=rho, scaling=scal)
+    b = vi.seeded_vector(dim, k, N, 46)
+    u0 = vi.seeded_vector(dim, k, N, 47)
+    with vps.Context(dim, k, N, 1, coef="learned") as ctx:
+        ctx.set_coefficient(dev(rho))
+        fb = ctx.mlp_infer_patches(0, dev(p, torch.float32))
+        assert fb == 0
+        u = dev(u0)
+        ctx.smooth(0, u, dev(b), sweeps=1)
+        assert rel(host(u), smoother.sweep_alg3(A, b, u0, P, S)) <= 1e-5
+        bad = p.copy()
+        bad[:] = np.nan
+        fb = ctx.mlp_infer_patches(0, dev(bad, torch.float32))
+        assert fb == len(P)
+        # the fallback scaling 1 is the plain rhobar-FDM smoother
+        S2 = smoother.LocalSolvers(A, P, "mean", rho=rho)
+        u = dev(u0)
+        ctx.smooth(0, u, dev(b), sweeps=1)
+        assert rel(host(u), smoother.sweep_alg3(A, b, u0, P, S2)) <= 1e-12
