@@ -1,0 +1,274 @@
+#!/usr/bin/env python
+"""Benchmark of the vertex-patch multigrid solver on one MI355X.
+
+One step = one complete solve A u = b to a relative residual of 1e-10 (CG from
+u = 0, preconditioned by the geometric-multigrid V-cycle whose smoother is the
+combined, colorized vertex-patch smoother), on a seeded synthetic right-hand
+side that is already resident in HBM.  The default workload is the 3D Q4
+Poisson problem on 128^3 cells (513^3 = 135,005,697 nodes), 6 levels, V(2,2),
+FP32 V-cycle inside FP64 flexible CG.
+
+Reported value: the smoother's throughput on the finest level, DoFs per
+second per sweep (nodes (kN+1)^d divided by the time of one sweep), with the
+sweep time measured by the library's HIP events around every finest-level
+sweep inside the K timed solves.  The JSON line also carries the solve time,
+the plain-FP64 solve time on the same right-hand side, the roofline of the
+smoother kernel and the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "patch_sweep_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_02100_amd", "csrc", f) for f in ("kernels.h", "patch_impl.h")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def color_counts(dim: int, k: int, n: int):
+    """Per color: (closure nodes of the color's patches, interior nodes written).
+
+    A color's patches sit at vertices v with fixed parity per direction; their
+    closures [k(v-1), k(v+1)] tile a contiguous node range per direction and
+    their interiors hold (2k-1) nodes per direction each.
+    """
+    out = []
+    for color in range(2 ** dim):
+        clo, inner = 1, 1
+        for e in range(dim):
+            v0 = 1 if (color >> e) & 1 else 2
+            npat = (n - 1 - v0) // 2 + 1 if v0 <= n - 1 else 0
+            vlast = v0 + 2 * (npat - 1)
+            clo *= (k * (vlast - v0 + 2) + 1) if npat > 0 else 0
+            inner *= (2 * k - 1) * npat
+        out.append((clo, inner))
+    return out
+
+
+def sweep_bytes(dim: int, k: int, n: int, word: int) -> int:
+    """Algorithmic bytes of one sweep: per color read the closures of u, read b and write u on the interiors."""
+    return sum((clo + 2 * inner) * word for clo, inner in color_counts(dim, k, n))
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle (FP64 NumPy/SciPy, Algorithm 3 with dense patch
+# solves) timed on a bounded sample of the same problem family.
+
+def oracle_child(n_cells: int, degree: int, dim: int, budget_s: float):
+    from oracle import assemble, smoother
+    import vps_inputs as vi
+    t0 = time.perf_counter()
+    A = assemble.assemble_kron(dim, degree, n_cells)
+    P = smoother.Patches(dim, degree, n_cells)
+    S = smoother.LocalSolvers(A, P, "shared")
+    b = vi.seeded_vector(dim, degree, n_cells, 5)
+    u = vi.seeded_vector(dim, degree, n_cells, 105)
+    setup = time.perf_counter() - t0
+    sweeps, t = 0, 0.0
+    while t < budget_s or sweeps < 1:
+        t1 = time.perf_counter()
+        u = smoother.sweep_alg3(A, b, u, P, S)
+        t += time.perf_counter() - t1
+        sweeps += 1
+    n = (degree * n_cells + 1) ** dim
+    print(json.dumps({"dofs": n, "sweeps": sweeps, "seconds": t, "setup_s": setup}))
+
+
+def cpu_baseline(dim: int, degree: int):
+    n_cells = 16 if dim == 3 else 128
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-child", str(n_cells), str(degree), str(dim)]
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    rate = d["dofs"] * d["sweeps"] / d["seconds"]
+    cpu = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": rate, "unit": "DoF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle smoother sweeps (Algorithm 3, assembled CSR + dense Cholesky patch solves, FP64, "
+                       f"single thread) on {dim}D Q{degree} with {n_cells}^{dim} cells "
+                       f"({d['dofs']} nodes), {d['sweeps']} sweeps in {d['seconds']:.1f} s; CPU: {cpu}; "
+                       f"host threads available: {len(os.sched_getaffinity(0))}")}
+
+
+# ---------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="poisson3d_q4_n128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64-reference", action="store_true")
+    ap.add_argument("--oracle-child", nargs=3, type=int, metavar=("N", "K", "D"))
+    args = ap.parse_args()
+
+    if args.oracle_child:
+        n, k, d = args.oracle_child
+        oracle_child(n, k, d, budget_s=12.0)
+        return 0
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build runs the smoother on a single MI355X "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented); use --gpus 1", file=sys.stderr)
+        return 2
+
+    import vps_inputs as vi
+    w = vi.WORKLOADS[args.workload]
+    dim, k, N = w["dim"], w["degree"], w["n_cells"]
+    if w["coef"] != "const":
+        print("bench.py times the constant-coefficient workloads", file=sys.stderr)
+        return 2
+
+    # the CPU baseline runs first, before this process touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(dim, k)
+
+    import torch
+    from paper_2407_02100_amd import vps
+
+    print(f"[bench] workload {args.workload}: generating the right-hand side", file=sys.stderr, flush=True)
+    b_host = vi.seeded_vector(dim, k, N, w["rhs_seed"])
+    n = b_host.size
+    b = torch.from_numpy(b_host).to("cuda")
+    del b_host
+    x = torch.empty_like(b)
+    word = 4 if w["vcycle"] == "f32" else 8
+
+    # measured copy bandwidth (context for the roofline)
+    src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+
+    ctx = vps.Context(dim, k, N, w["levels"], w["pre"], w["post"], vcycle_dtype=w["vcycle"])
+    print(f"[bench] warmup {args.warmup} solves", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ctx.solve(b, x, rtol=1e-10, maxit=100)
+    ctx.timing_enable(True)
+    print(f"[bench] timing {args.steps} solves", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [ctx.solve(b, x, rtol=1e-10, maxit=100) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tim = ctx.timing_get()
+    ctx.timing_enable(False)
+    ctx.close()
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+
+    L = w["levels"] - 1
+    sweeps = tim["smooth_sweeps"][L]
+    t_sm = tim["smooth_s"][L]
+    value = n * sweeps / t_sm
+    launches = sweeps * 2 ** dim
+    bytes_sweep = sweep_bytes(dim, k, N, word)
+    per_launch_s = t_sm / launches
+    achieved = bytes_sweep / 2 ** dim / per_launch_s / 1e9
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("workload") == args.workload:
+            traffic = tr.get("bytes_per_launch")
+
+    f64 = None
+    if not args.no_f64_reference and w["vcycle"] == "f32":
+        print("[bench] plain FP64 reference solve", file=sys.stderr, flush=True)
+        ctx64 = vps.Context(dim, k, N, w["levels"], w["pre"], w["post"], vcycle_dtype="f64")
+        ctx64.solve(b, x, rtol=1e-10, maxit=100)
+        ctx64.timing_enable(True)
+        i64 = ctx64.solve(b, x, rtol=1e-10, maxit=100)
+        t64 = ctx64.timing_get()
+        ctx64.close()
+        f64 = {"solve_s": i64["seconds"], "iterations": i64["iterations"],
+               "rel_residual_true": i64["rel_residual_true"],
+               "smoother_dof_per_s": n * t64["smooth_sweeps"][L] / t64["smooth_s"][L],
+               "smoother_gbs": sweep_bytes(dim, k, N, 8) * t64["smooth_sweeps"][L] / t64["smooth_s"][L] / 1e9}
+
+    solve_s = sum(i["seconds"] for i in infos) / len(infos)
+    total_phases = (sum(tim["smooth_s"]) + sum(tim["residual_s"]) + sum(tim["restrict_s"]) +
+                    sum(tim["prolong_s"]) + tim["coarse_s"] + tim["cg_operator_s"] + tim["cg_vector_s"])
+    out = {
+        "metric": "smoother DoF/s, % HBM peak; solve time to 1e-10, plain vs mixed/learned",
+        "value": value,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if w["vcycle"] == "f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload,
+                   "problem": f"-Laplace(u)=f on [0,1]^{dim}, Q{k}, {N}^{dim} cells, {n} nodes",
+                   "levels": w["levels"], "cycle": f"V({w['pre']},{w['post']})",
+                   "vcycle_dtype": w["vcycle"], "outer": "FP64 flexible CG" if w["vcycle"] == "f32" else "FP64 PCG",
+                   "rtol": 1e-10, "rhs": f"uniform [-1,1] on free nodes, seed {w['rhs_seed']}"},
+        "solve": {"seconds": solve_s, "iterations": infos[-1]["iterations"],
+                  "rel_residual_true": max(i["rel_residual_true"] for i in infos),
+                  "vcycles_timed": tim["vcycles"]},
+        "plain_f64": f64,
+        "speedup_mixed_vs_f64": (f64["solve_s"] / solve_s) if f64 else None,
+        "phase_split": {
+            "smooth_finest": t_sm / total_phases,
+            "smooth_coarser": (sum(tim["smooth_s"]) - t_sm) / total_phases,
+            "residual": sum(tim["residual_s"]) / total_phases,
+            "transfer": (sum(tim["restrict_s"]) + sum(tim["prolong_s"])) / total_phases,
+            "coarse": tim["coarse_s"] / total_phases,
+            "cg_operator": tim["cg_operator_s"] / total_phases,
+            "cg_vector": tim["cg_vector_s"] / total_phases,
+        },
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "patch_color_kernel (one color of the smoother, finest level)",
+                     "avg_launch_us": per_launch_s * 1e6, "bytes_per_launch": bytes_sweep / 2 ** dim,
+                     "measured_copy_gbs": copy_gbs},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -71,7 +71,7 @@ typedef struct {
   int dim;               /* 2 or 3 */
   int degree;            /* k, 1..4 */
   int n_cells;           /* N on the finest level; divisible by 2^(n_levels-1) */
-  int n_levels;          /* >= 1; coarsest level must have >= 2 cells per direction */
+  int n_levels;          /* 1..16; coarsest level must have >= 2 cells per direction */
   int pre_sweeps;        /* forward sweeps before the coarse correction, >= 0 */
   int post_sweeps;       /* reverse sweeps after it, >= 0 */
   int vcycle_dtype;      /* vps_dtype of everything inside the V-cycle */
@@ -228,6 +228,31 @@ vps_status vps_mlp_adam(vps_context* ctx, float* params, const float* dparams, f
  * fallback (host, may be NULL) receives their number.  Synchronises. */
 vps_status vps_mlp_infer_patches(vps_context* ctx, int level, const float* params,
                                  long long* fallback);
+
+/* ---- phase timing (the time split of the multigrid solve) ---- */
+
+#define VPS_MAX_LEVELS 16
+
+typedef struct {
+  int n_levels;
+  double smooth_s[VPS_MAX_LEVELS];          /* smoother sweeps, per level */
+  long long smooth_sweeps[VPS_MAX_LEVELS];  /* sweeps done, per level (2^d color launches each) */
+  double residual_s[VPS_MAX_LEVELS];        /* r = b - A u inside the V-cycle, per level */
+  double restrict_s[VPS_MAX_LEVELS];        /* restriction from this level to the next coarser */
+  double prolong_s[VPS_MAX_LEVELS];         /* prolongation from the next coarser to this level */
+  double coarse_s;                          /* coarse solves */
+  double cg_operator_s;                     /* CG matrix-vector products (finest level, FP64) */
+  double cg_vector_s;                       /* CG dots, updates, precision conversions */
+  long long vcycles;
+} vps_timing;
+
+/* enable != 0: from now on record HIP events on the context's stream around
+ * every phase (small overhead) and reset the totals; 0: stop recording. */
+vps_status vps_timing_enable(vps_context* ctx, int enable);
+
+/* Totals of the recorded phases since the last vps_timing_enable(ctx, 1).
+ * Synchronises. */
+vps_status vps_timing_get(vps_context* ctx, vps_timing* out);
 
 /* ---- misc ---- */
 

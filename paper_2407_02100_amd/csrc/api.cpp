@@ -39,6 +39,22 @@ struct Level {
   Mat Mc, Kc;               // cell matrices (h-scaled)
 };
 
+enum Phase { PH_SMOOTH, PH_RESIDUAL, PH_RESTRICT, PH_PROLONG, PH_COARSE, PH_CG_OP, PH_CG_VEC };
+
+// Event pairs recorded around phases; resolved (synchronously) by flush().
+struct PhaseTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec {
+    int phase, level;
+    hipEvent_t a, b;
+    long long sweeps;
+  };
+  std::vector<Rec> recs;
+  vps_timing tot{};
+};
+
 }  // namespace
 
 struct vps_context {
@@ -68,6 +84,7 @@ struct vps_context {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // MLP work
   vps::MlpWork mlp;
+  PhaseTimer timer;
 };
 
 namespace {
@@ -107,6 +124,61 @@ template <typename F>
 hipError_t dispatch_tkd(vps_dtype t, int k, int d, F&& f) {
   if (t == VPS_F64) return dispatch_kd<double>(k, d, f);
   return dispatch_kd<float>(k, d, f);
+}
+
+hipError_t timer_flush(vps_context* c);
+
+// Start a phase; returns its record index or -1 when timing is off.
+int tbegin(vps_context* c, int phase, int level, long long sweeps = 0) {
+  PhaseTimer& T = c->timer;
+  if (!T.on) return -1;
+  if (T.used + 2 > T.pool.size()) {
+    if (T.used >= 4096) {
+      if (timer_flush(c) != hipSuccess) return -1;
+    } else {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        T.pool.push_back(e);
+      }
+    }
+  }
+  PhaseTimer::Rec r{phase, level, T.pool[T.used], T.pool[T.used + 1], sweeps};
+  T.used += 2;
+  if (hipEventRecord(r.a, c->stream) != hipSuccess) return -1;
+  T.recs.push_back(r);
+  return (int)T.recs.size() - 1;
+}
+
+void tend(vps_context* c, int idx) {
+  if (idx < 0) return;
+  (void)hipEventRecord(c->timer.recs[idx].b, c->stream);
+}
+
+hipError_t timer_flush(vps_context* c) {
+  PhaseTimer& T = c->timer;
+  if (T.recs.empty()) return hipSuccess;
+  hipError_t e = hipEventSynchronize(T.recs.back().b);
+  if (e != hipSuccess) return e;
+  for (const auto& r : T.recs) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return e;
+    const double s = ms * 1e-3;
+    const int l = r.level < VPS_MAX_LEVELS ? r.level : VPS_MAX_LEVELS - 1;
+    switch (r.phase) {
+      case PH_SMOOTH: T.tot.smooth_s[l] += s; T.tot.smooth_sweeps[l] += r.sweeps; break;
+      case PH_RESIDUAL: T.tot.residual_s[l] += s; break;
+      case PH_RESTRICT: T.tot.restrict_s[l] += s; break;
+      case PH_PROLONG: T.tot.prolong_s[l] += s; break;
+      case PH_COARSE: T.tot.coarse_s += s; break;
+      case PH_CG_OP: T.tot.cg_operator_s += s; break;
+      default: T.tot.cg_vector_s += s; break;
+    }
+  }
+  T.recs.clear();
+  T.used = 0;
+  return hipSuccess;
 }
 
 size_t esize(vps_dtype t) { return t == VPS_F64 ? sizeof(double) : sizeof(float); }
@@ -325,28 +397,50 @@ hipError_t do_coarse(vps_context* c, const void* b, void* x, vps_dtype t) {
 
 hipError_t vcycle_level(vps_context* c, int l, const void* b, void* u) {
   const vps_dtype t = vdt(c);
-  if (l == 0) return do_coarse(c, b, u, t);
-  Level& L = c->lv[l];
   hipError_t e;
+  if (l == 0) {
+    const int i0 = tbegin(c, PH_COARSE, 0);
+    e = do_coarse(c, b, u, t);
+    tend(c, i0);
+    return e;
+  }
+  Level& L = c->lv[l];
+  int ti = tbegin(c, PH_SMOOTH, l, c->cfg.pre_sweeps);
   if (t == VPS_F64) e = vps::launch_fill<double>(u, 0.0, L.nodes, c->stream);
   else e = vps::launch_fill<float>(u, 0.0, L.nodes, c->stream);
   if (e != hipSuccess) return e;
   if ((e = do_smooth(c, l, u, b, t, c->cfg.pre_sweeps, false)) != hipSuccess) return e;
+  tend(c, ti);
+  ti = tbegin(c, PH_RESIDUAL, l);
   if ((e = do_operator(c, l, u, b, L.r, t)) != hipSuccess) return e;
+  tend(c, ti);
+  ti = tbegin(c, PH_RESTRICT, l);
   if ((e = do_restrict(c, l, L.r, c->lv[l - 1].b, t)) != hipSuccess) return e;
+  tend(c, ti);
   if ((e = vcycle_level(c, l - 1, c->lv[l - 1].b, c->lv[l - 1].u)) != hipSuccess) return e;
+  ti = tbegin(c, PH_PROLONG, l);
   if ((e = do_prolong(c, l, c->lv[l - 1].u, u, t)) != hipSuccess) return e;
-  return do_smooth(c, l, u, b, t, c->cfg.post_sweeps, true);
+  tend(c, ti);
+  ti = tbegin(c, PH_SMOOTH, l, c->cfg.post_sweeps);
+  e = do_smooth(c, l, u, b, t, c->cfg.post_sweeps, true);
+  tend(c, ti);
+  return e;
 }
 
 hipError_t do_vcycle(vps_context* c, const double* r, double* z) {
   const int L = (int)c->lv.size() - 1;
+  if (c->timer.on) c->timer.tot.vcycles += 1;
   if (vdt(c) == VPS_F64) return vcycle_level(c, L, r, z);
   Level& F = c->lv[L];
+  int ti = tbegin(c, PH_CG_VEC, L);
   hipError_t e = vps::launch_cast<double, float>(r, F.b, F.nodes, c->stream);
   if (e != hipSuccess) return e;
+  tend(c, ti);
   if ((e = vcycle_level(c, L, F.b, F.u)) != hipSuccess) return e;
-  return vps::launch_cast<float, double>(F.u, z, F.nodes, c->stream);
+  ti = tbegin(c, PH_CG_VEC, L);
+  e = vps::launch_cast<float, double>(F.u, z, F.nodes, c->stream);
+  tend(c, ti);
+  return e;
 }
 
 vps_status need_coarse(vps_context* c) {
@@ -410,6 +504,7 @@ void free_all(vps_context* c) {
   if (c->hscal) hipHostFree(c->hscal);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->timer.pool) hipEventDestroy(e);
   vps::mlp_free(&c->mlp);
 }
 
@@ -432,7 +527,7 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.dim != 2 && C.dim != 3) return VPS_E_UNSUPPORTED;
   if (C.degree < 1 || C.degree > 4) return VPS_E_UNSUPPORTED;
   if (C.n_levels < 1 || C.n_cells < 2) return VPS_E_UNSUPPORTED;
-  if (C.n_levels > 30 || C.n_cells % (1 << (C.n_levels - 1)) != 0) return VPS_E_UNSUPPORTED;
+  if (C.n_levels > VPS_MAX_LEVELS || C.n_cells % (1 << (C.n_levels - 1)) != 0) return VPS_E_UNSUPPORTED;
   const int n0 = C.n_cells >> (C.n_levels - 1);
   if (n0 < 2) return VPS_E_UNSUPPORTED;
   if (C.pre_sweeps < 0 || C.post_sweeps < 0) return VPS_E_ARG;
@@ -694,7 +789,9 @@ vps_status vps_smooth(vps_context* c, int level, void* u, const void* b, vps_dty
   if (t != VPS_F64 && t != VPS_F32) return fail(c, VPS_E_ARG, "invalid dtype");
   if (sweeps < 0) return fail(c, VPS_E_ARG, "negative sweeps");
   if (vps_status s = need_coef(c)) return s;
+  const int ti = tbegin(c, PH_SMOOTH, level, sweeps);
   VPS_HIP(c, do_smooth(c, level, u, b, t, sweeps, reverse != 0));
+  tend(c, ti);
   return VPS_OK;
 }
 
@@ -736,7 +833,10 @@ vps_status vps_solve(vps_context* c, const double* b, double* x, double rtol, in
     int it = 0;
     while (it < maxit) {
       ++it;
+      int ti = tbegin(c, PH_CG_OP, L);
       VPS_HIP(c, do_operator(c, L, p, nullptr, q, VPS_F64));
+      tend(c, ti);
+      ti = tbegin(c, PH_CG_VEC, L);
       if (vps_status st = dots(c, p, q, nullptr, nullptr, n, s2)) return st;
       const double pq = s2[0];
       const double alpha = rz / pq;
@@ -750,6 +850,7 @@ vps_status vps_solve(vps_context* c, const double* b, double* x, double rtol, in
       VPS_HIP(c, vps::launch_dot_final(c->partial, nblk, 1, c->dscal, c->stream));
       VPS_HIP(c, hipMemcpyAsync(c->hscal, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
       VPS_HIP(c, hipStreamSynchronize(c->stream));
+      tend(c, ti);
       double rn = std::sqrt(c->hscal[0]);
       inf.iterations = it;
       if (!std::isfinite(rn)) {
@@ -769,6 +870,7 @@ vps_status vps_solve(vps_context* c, const double* b, double* x, double rtol, in
         restarted = true;
       }
       VPS_HIP(c, do_vcycle(c, r, z));
+      ti = tbegin(c, PH_CG_VEC, L);
       double rzn, zq;
       if (flexible && !restarted) {
         if (vps_status st = dots(c, r, z, z, q, n, s2)) return st;
@@ -787,6 +889,7 @@ vps_status vps_solve(vps_context* c, const double* b, double* x, double rtol, in
         break;
       }
       VPS_HIP(c, vps::launch_xpay(z, beta, p, n, c->stream));
+      tend(c, ti);
     }
   }
   // final true residual
@@ -795,7 +898,8 @@ vps_status vps_solve(vps_context* c, const double* b, double* x, double rtol, in
   VPS_HIP(c, hipEventRecord(c->ev1, c->stream));
   VPS_HIP(c, hipEventSynchronize(c->ev1));
   float ms = 0.f;
-  hipEventElapsedTime(&ms, c->ev0, c->ev1);
+  VPS_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  VPS_HIP(c, timer_flush(c));
   inf.rel_residual_true = bn > 0.0 ? std::sqrt(s2[0]) / bn : 0.0;
   inf.seconds = ms * 1e-3;
   if (info) *info = inf;
@@ -823,6 +927,25 @@ vps_status vps_vcycle_iterate(vps_context* c, const double* b, double* u, int it
     VPS_HIP(c, vps::launch_axpy<double>(1.0, c->cg_z, u, n, c->stream));
   }
   VPS_HIP(c, hipStreamSynchronize(c->stream));
+  return VPS_OK;
+}
+
+vps_status vps_timing_enable(vps_context* c, int enable) {
+  if (!c) return VPS_E_ARG;
+  VPS_HIP(c, timer_flush(c));
+  c->timer.on = enable != 0;
+  if (c->timer.on) {
+    c->timer.tot = vps_timing{};
+    c->timer.tot.n_levels = (int)c->lv.size();
+  }
+  return VPS_OK;
+}
+
+vps_status vps_timing_get(vps_context* c, vps_timing* out) {
+  if (!c || !out) return VPS_E_ARG;
+  VPS_HIP(c, timer_flush(c));
+  *out = c->timer.tot;
+  out->n_levels = (int)c->lv.size();
   return VPS_OK;
 }
 

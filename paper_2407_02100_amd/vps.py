@@ -42,6 +42,20 @@ class vps_solve_info(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("fallback_patches", ctypes.c_longlong)]
 
 
+VPS_MAX_LEVELS = 16
+
+
+class vps_timing(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int),
+                ("smooth_s", ctypes.c_double * VPS_MAX_LEVELS),
+                ("smooth_sweeps", ctypes.c_longlong * VPS_MAX_LEVELS),
+                ("residual_s", ctypes.c_double * VPS_MAX_LEVELS),
+                ("restrict_s", ctypes.c_double * VPS_MAX_LEVELS),
+                ("prolong_s", ctypes.c_double * VPS_MAX_LEVELS),
+                ("coarse_s", ctypes.c_double), ("cg_operator_s", ctypes.c_double),
+                ("cg_vector_s", ctypes.c_double), ("vcycles", ctypes.c_longlong)]
+
+
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _ll = ctypes.c_longlong
@@ -75,6 +89,8 @@ SIGNATURES = {
     "vps_mlp_backward": (_i, [_vp, _vp, _vp, _vp, _vp, _ll, _vp]),
     "vps_mlp_adam": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _f, _f, _f, _f]),
     "vps_mlp_infer_patches": (_i, [_vp, _i, _vp, ctypes.POINTER(_ll)]),
+    "vps_timing_enable": (_i, [_vp, _i]),
+    "vps_timing_get": (_i, [_vp, ctypes.POINTER(vps_timing)]),
     "vps_sync": (_i, [_vp]),
     "vps_status_string": (ctypes.c_char_p, [_i]),
     "vps_last_error": (ctypes.c_char_p, [_vp]),
@@ -262,6 +278,18 @@ class Context:
                     "vps_mlp_infer_patches")
         return int(fb.value)
 
+    def timing_enable(self, enable=True):
+        self._check(lib().vps_timing_enable(self.h, int(enable)), "vps_timing_enable")
+
+    def timing_get(self):
+        t = vps_timing()
+        self._check(lib().vps_timing_get(self.h, ctypes.byref(t)), "vps_timing_get")
+        L = t.n_levels
+        return {"n_levels": L, "smooth_s": list(t.smooth_s[:L]), "smooth_sweeps": list(t.smooth_sweeps[:L]),
+                "residual_s": list(t.residual_s[:L]), "restrict_s": list(t.restrict_s[:L]),
+                "prolong_s": list(t.prolong_s[:L]), "coarse_s": t.coarse_s, "cg_operator_s": t.cg_operator_s,
+                "cg_vector_s": t.cg_vector_s, "vcycles": t.vcycles}
+
     def sync(self):
         self._check(lib().vps_sync(self.h), "vps_sync")
 
@@ -281,7 +309,8 @@ def _method_alias(name):
 for _n in ("destroy", "set_stream", "level_nodes", "level_cells", "level_patches", "set_coefficient",
            "set_patch_scaling", "apply", "residual", "restrict", "prolongate_add", "coarse_solve",
            "smooth_color", "smooth", "vcycle", "solve", "vcycle_iterate", "patch_features", "patch_targets",
-           "mlp_forward", "mlp_loss_grad", "mlp_backward", "mlp_adam", "mlp_infer_patches", "sync"):
+           "mlp_forward", "mlp_loss_grad", "mlp_backward", "mlp_adam", "mlp_infer_patches", "timing_enable",
+           "timing_get", "sync"):
     globals()["vps_" + _n] = _method_alias(_n)
 
 
