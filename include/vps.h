@@ -76,7 +76,9 @@ typedef struct {
   int post_sweeps;       /* reverse sweeps after it, >= 0 */
   int vcycle_dtype;      /* vps_dtype of everything inside the V-cycle */
   int coef;              /* vps_coef */
-  int patches_per_block; /* patches along x per workgroup, 0 = automatic */
+  int patches_per_block; /* 0 = automatic (3D rho = 1: one patch per wavefront);
+                            1, 2, 4 = batches of that many patches along x per
+                            256-thread workgroup */
 } vps_config;
 
 typedef struct {

@@ -33,6 +33,9 @@ struct Level {
   Mat Mfull, Kfull, Mh[2], Kh[2];
   Mat T1;                   // FDM eigenvectors (q x q)
   std::vector<double> lam;  // FDM eigenvalues (q)
+  Mat Te, To;               // even/odd blocks of T1 (symmetric / antisymmetric modes)
+  std::vector<double> ilam; // 1 / (lam_a + lam_b [+ lam_c]) in the even/odd mode order
+  void* ilam_dev[2] = {nullptr, nullptr};  // [0] FP64, [1] FP32
   Mat opM, opK;             // operator tile blocks
   Mat restrictG;            // transfer tile: this level -> level-1
   Mat prolongG;             // transfer tile: level-1 -> this level
@@ -226,6 +229,16 @@ void build_level(Level& L, int k, int d, int ncell) {
       Ki[o * q + j] = Kp[(o + 1) * p + j + 1];
     }
   vps::gen_eig(q, Mi, Ki, &L.T1, &L.lam);
+  std::vector<int> order;
+  if (!vps::fdm_even_odd(q, L.T1, &L.Te, &L.To, &order)) {
+    L.Te.clear();  // no even/odd structure: the one-patch-per-wave kernel is not used
+  } else if (d == 3) {
+    L.ilam.assign((size_t)q * q * q, 0.0);
+    for (int jz = 0; jz < q; ++jz)
+      for (int jy = 0; jy < q; ++jy)
+        for (int jx = 0; jx < q; ++jx)
+          L.ilam[((size_t)jz * q + jy) * q + jx] = 1.0 / (L.lam[order[jx]] + L.lam[order[jy]] + L.lam[order[jz]]);
+  }
   // operator tile
   {
     const int TC = vps::op_tc(k, d);
@@ -299,8 +312,7 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   P.ncell = L.ncell;
   P.color = color;
   P.coef = coef;
-  P.pb = c->cfg.patches_per_block > 0 ? c->cfg.patches_per_block
-                                       : vps::default_patches_per_block(k, d, coef, t == VPS_F64);
+  P.pb = c->cfg.patches_per_block;  // 0: the launcher chooses
   if (coef == VPS_COEF_CONST) {
     P.M[0] = L.Mfull.data();
     P.M[1] = nullptr;
@@ -314,6 +326,10 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   }
   P.T1 = L.T1.data();
   P.lam = L.lam.data();
+  P.Te = L.Te.empty() ? nullptr : L.Te.data();
+  P.To = L.Te.empty() ? nullptr : L.To.data();
+  P.ilam = L.ilam_dev[t == VPS_F64 ? 0 : 1];
+  if (!P.ilam || !P.Te) P.pb = P.pb > 0 ? P.pb : -1;  // -1: generic kernel, automatic batch
   return dispatch_tkd(t, k, d, [&]<typename T, int K, int D>() { return vps::launch_patch_color<T, K, D>(P, c->stream); });
 }
 
@@ -488,6 +504,8 @@ void free_all(vps_context* c) {
     hipFree(L.rho64);
     hipFree(L.rho32);
     hipFree(L.scal);
+    hipFree(L.ilam_dev[0]);
+    hipFree(L.ilam_dev[1]);
   }
   for (int i = 0; i < 2; ++i) {
     hipFree(c->cT0[i]);
@@ -552,6 +570,10 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
     return s;
   };
   for (Level& L : c->lv) {
+    if (!L.ilam.empty() && C.coef == VPS_COEF_CONST) {
+      if (upload<double>(L.ilam, &L.ilam_dev[0], c->stream) != hipSuccess) return bail(VPS_E_HIP);
+      if (upload<float>(L.ilam, &L.ilam_dev[1], c->stream) != hipSuccess) return bail(VPS_E_HIP);
+    }
     if (hipMalloc(&L.u, L.nodes * esize(t)) != hipSuccess) return bail(VPS_E_NOMEM);
     if (hipMalloc(&L.b, L.nodes * esize(t)) != hipSuccess) return bail(VPS_E_NOMEM);
     if (hipMalloc(&L.r, L.nodes * esize(t)) != hipSuccess) return bail(VPS_E_NOMEM);

@@ -222,6 +222,33 @@ void gen_eig(int n, const Mat& M, const Mat& K, Mat* T, std::vector<double>* lam
   }
 }
 
+bool fdm_even_odd(int q, const Mat& T, Mat* Te, Mat* To, std::vector<int>* order) {
+  const int ne = (q + 1) / 2, no = (q - 1) / 2;
+  std::vector<int> ev, od;
+  for (int m = 0; m < q; ++m) {
+    double scale = 0.0, es = 0.0, os = 0.0;
+    for (int i = 0; i < q; ++i) scale = std::max(scale, std::fabs(T[i * q + m]));
+    for (int i = 0; i < q; ++i) {
+      es = std::max(es, std::fabs(T[(q - 1 - i) * q + m] - T[i * q + m]));
+      os = std::max(os, std::fabs(T[(q - 1 - i) * q + m] + T[i * q + m]));
+    }
+    if (es <= 1e-10 * scale) ev.push_back(m);
+    else if (os <= 1e-10 * scale) od.push_back(m);
+    else return false;
+  }
+  if ((int)ev.size() != ne || (int)od.size() != no) return false;
+  Te->assign(ne * ne, 0.0);
+  To->assign(std::max(no * no, 1), 0.0);
+  for (int j = 0; j < ne; ++j)
+    for (int i = 0; i < ne; ++i) (*Te)[i * ne + j] = T[i * q + ev[j]];
+  for (int j = 0; j < no; ++j)
+    for (int i = 0; i < no; ++i) (*To)[i * no + j] = T[i * q + od[j]];
+  order->clear();
+  for (int m : ev) order->push_back(m);
+  for (int m : od) order->push_back(m);
+  return true;
+}
+
 bool spd_inverse(int n, Mat* A) {
   Mat L = *A;
   if (!cholesky_lower(n, &L)) return false;

@@ -39,6 +39,14 @@ void assemble_1d(int k, int ncell, double h, Mat* M, Mat* K, const double* cell_
 // Cholesky of M, then cyclic Jacobi on L^{-1} K L^{-T}.
 void gen_eig(int n, const Mat& M, const Mat& K, Mat* T, std::vector<double>* lambda);
 
+// Split the eigenvectors of a reversal-symmetric 1D problem (q odd) into the
+// symmetric ones (T[q-1-i][m] = T[i][m], (q+1)/2 of them) and the
+// antisymmetric ones ((q-1)/2), each group in ascending eigenvalue order.
+// Te: (q+1)/2 x (q+1)/2, rows i = 0..(q-1)/2; To: (q-1)/2 x (q-1)/2, rows
+// i = 0..(q-3)/2.  order[j] = original mode of internal mode j (symmetric
+// first).  Returns false if some eigenvector is neither (tolerance 1e-10).
+bool fdm_even_odd(int q, const Mat& T, Mat* Te, Mat* To, std::vector<int>* order);
+
 // In-place inverse of an SPD matrix (Cholesky, then L^{-T} L^{-1}).
 // Returns false if the matrix is not numerically SPD.
 bool spd_inverse(int n, Mat* A);

@@ -34,6 +34,11 @@ struct PatchLaunch {
   const double* Kst[2];
   const double* T1;    // Q x Q
   const double* lam;   // Q
+  // one-patch-per-wavefront kernel (3D, rho = 1): even/odd blocks of T and the
+  // reciprocal eigenvalue sums in the internal mode order (device, dtype of u)
+  const double* Te;    // K x K
+  const double* To;    // (K-1) x (K-1)
+  const void* ilam;    // Q^3
 };
 
 template <typename T, int K, int D>

@@ -59,10 +59,36 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
     }
   for (int i = 0; i < Q * Q; ++i) a.m.T1[i] = (T)L.T1[i];
   for (int i = 0; i < Q; ++i) a.m.lam[i] = (T)L.lam[i];
+  if (D == 3 && L.coef == 0 && L.pb == 0) {
+    if constexpr (K >= 2) {
+      static_assert(sizeof(WaveArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
+      WaveArgs<T, K> w;
+      w.u = a.u;
+      w.b = a.b;
+      w.ilam = (const T*)L.ilam;
+      w.n1 = a.n1;
+      for (int e = 0; e < 3; ++e) {
+        w.v0[e] = a.v0[e];
+        w.np[e] = a.np[e];
+      }
+      w.npatch = (unsigned)a.np[0] * (unsigned)a.np[1] * (unsigned)a.np[2];
+      for (int i = 0; i < Q * P; ++i) {
+        w.M[i] = a.m.M[0][i];
+        w.Kst[i] = a.m.Kst[0][i];
+      }
+      for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
+      for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
+      // one wave per patch; the grid is padded to a multiple of the XCD count
+      const unsigned grid = (w.npatch + kXcd - 1) / kXcd * kXcd;
+      patch_wave3_kernel<T, K><<<grid, 64, 0, s>>>(w);
+      return hipGetLastError();
+    }
+  }
+  const int pb = L.pb > 0 ? L.pb : default_patches_per_block(K, D, L.coef, sizeof(T) == 8);  // 0, -1: automatic
   switch (L.coef) {
-    case 0: return go_patch_pb<T, K, D, 0>(a, L.pb, s);
-    case 1: return go_patch_pb<T, K, D, 1>(a, L.pb, s);
-    case 2: return go_patch_pb<T, K, D, 2>(a, L.pb, s);
+    case 0: return go_patch_pb<T, K, D, 0>(a, pb, s);
+    case 1: return go_patch_pb<T, K, D, 1>(a, pb, s);
+    case 2: return go_patch_pb<T, K, D, 2>(a, pb, s);
     default: return hipErrorInvalidValue;
   }
 }
