@@ -264,7 +264,8 @@ vps_status vps_sync(vps_context* ctx);
 /* Static description of a status code. */
 const char* vps_status_string(vps_status s);
 
-/* Message of the last error on this context ("" if none); valid until the next call. */
+/* Message of the last error on this context ("" if none); valid until the next
+ * call.  ctx = NULL: message of the calling thread's last failed vps_create. */
 const char* vps_last_error(const vps_context* ctx);
 
 #ifdef __cplusplus

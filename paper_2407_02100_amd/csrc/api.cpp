@@ -94,6 +94,9 @@ namespace {
 
 constexpr int kMaxDenseCoarse = 4096;
 
+// message of the last failed vps_create (no context exists then)
+thread_local std::string g_create_error;
+
 const char* kStatusText[] = {"ok",           "invalid argument", "unsupported configuration",
                              "HIP error",    "out of device memory", "not converged",
                              "non-finite value", "invalid state"};
@@ -536,7 +539,7 @@ const char* vps_status_string(vps_status s) {
   return kStatusText[i];
 }
 
-const char* vps_last_error(const vps_context* ctx) { return ctx ? ctx->err.c_str() : ""; }
+const char* vps_last_error(const vps_context* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
 vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out) {
   if (!cfg || !out) return VPS_E_ARG;
@@ -564,30 +567,38 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   c->fallback.assign(C.n_levels, 0);
   for (int l = 0; l < C.n_levels; ++l) build_level(c->lv[l], C.degree, C.dim, n0 << l);
 
+  hipError_t last = hipSuccess;
+  const char* what = "";
   auto bail = [&](vps_status s) {
+    g_create_error = std::string("vps_create: ") + what + (last != hipSuccess ? std::string(": ") + hipGetErrorString(last) : "");
     free_all(c);
     delete c;
     return s;
   };
+  auto chk = [&](hipError_t e, const char* w) {
+    last = e;
+    what = w;
+    return e != hipSuccess;
+  };
   for (Level& L : c->lv) {
     if (!L.ilam.empty() && C.coef == VPS_COEF_CONST) {
-      if (upload<double>(L.ilam, &L.ilam_dev[0], c->stream) != hipSuccess) return bail(VPS_E_HIP);
-      if (upload<float>(L.ilam, &L.ilam_dev[1], c->stream) != hipSuccess) return bail(VPS_E_HIP);
+      if (chk(upload<double>(L.ilam, &L.ilam_dev[0], c->stream), "upload")) return bail(VPS_E_HIP);
+      if (chk(upload<float>(L.ilam, &L.ilam_dev[1], c->stream), "upload")) return bail(VPS_E_HIP);
     }
-    if (hipMalloc(&L.u, L.nodes * esize(t)) != hipSuccess) return bail(VPS_E_NOMEM);
-    if (hipMalloc(&L.b, L.nodes * esize(t)) != hipSuccess) return bail(VPS_E_NOMEM);
-    if (hipMalloc(&L.r, L.nodes * esize(t)) != hipSuccess) return bail(VPS_E_NOMEM);
+    if (chk(hipMalloc(&L.u, L.nodes * esize(t)), "hipMalloc")) return bail(VPS_E_NOMEM);
+    if (chk(hipMalloc(&L.b, L.nodes * esize(t)), "hipMalloc")) return bail(VPS_E_NOMEM);
+    if (chk(hipMalloc(&L.r, L.nodes * esize(t)), "hipMalloc")) return bail(VPS_E_NOMEM);
     if (C.coef != VPS_COEF_CONST) {
       size_t cells = 1;
       for (int e = 0; e < C.dim; ++e) cells *= (size_t)L.ncell;
-      if (hipMalloc(&L.rho64, cells * sizeof(double)) != hipSuccess) return bail(VPS_E_NOMEM);
-      if (hipMalloc(&L.rho32, cells * sizeof(float)) != hipSuccess) return bail(VPS_E_NOMEM);
+      if (chk(hipMalloc(&L.rho64, cells * sizeof(double)), "hipMalloc")) return bail(VPS_E_NOMEM);
+      if (chk(hipMalloc(&L.rho32, cells * sizeof(float)), "hipMalloc")) return bail(VPS_E_NOMEM);
     }
     if (C.coef == VPS_COEF_CELL_LEARNED) {
       const size_t n = (size_t)L.npatch * ipow(2 * C.degree - 1, C.dim);
       if (n > 0) {
-        if (hipMalloc(&L.scal, n * sizeof(float)) != hipSuccess) return bail(VPS_E_NOMEM);
-        if (vps::launch_fill<float>(L.scal, 1.0, n, c->stream) != hipSuccess) return bail(VPS_E_HIP);
+        if (chk(hipMalloc(&L.scal, n * sizeof(float)), "hipMalloc")) return bail(VPS_E_NOMEM);
+        if (chk(vps::launch_fill<float>(L.scal, 1.0, n, c->stream), "fill")) return bail(VPS_E_HIP);
       }
     }
   }
@@ -607,17 +618,17 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
     std::vector<double> lam0;
     vps::gen_eig(m, Mi, Ki, &T0, &lam0);
     c->cn0 = m;
-    if (upload<double>(T0, &c->cT0[0], c->stream) != hipSuccess) return bail(VPS_E_HIP);
-    if (upload<double>(lam0, &c->clam0[0], c->stream) != hipSuccess) return bail(VPS_E_HIP);
-    if (upload<float>(T0, &c->cT0[1], c->stream) != hipSuccess) return bail(VPS_E_HIP);
-    if (upload<float>(lam0, &c->clam0[1], c->stream) != hipSuccess) return bail(VPS_E_HIP);
+    if (chk(upload<double>(T0, &c->cT0[0], c->stream), "upload")) return bail(VPS_E_HIP);
+    if (chk(upload<double>(lam0, &c->clam0[0], c->stream), "upload")) return bail(VPS_E_HIP);
+    if (chk(upload<float>(T0, &c->cT0[1], c->stream), "upload")) return bail(VPS_E_HIP);
+    if (chk(upload<float>(lam0, &c->clam0[1], c->stream), "upload")) return bail(VPS_E_HIP);
     c->coarse_ok = true;
   }
-  if (hipMalloc(&c->partial, 2 * vps::kDotBlocks * sizeof(double)) != hipSuccess) return bail(VPS_E_NOMEM);
-  if (hipMalloc(&c->dscal, 4 * sizeof(double)) != hipSuccess) return bail(VPS_E_NOMEM);
-  if (hipHostMalloc(&c->hscal, 4 * sizeof(double), 0) != hipSuccess) return bail(VPS_E_NOMEM);
-  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) return bail(VPS_E_HIP);
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(VPS_E_HIP);
+  if (chk(hipMalloc(&c->partial, 2 * vps::kDotBlocks * sizeof(double)), "hipMalloc")) return bail(VPS_E_NOMEM);
+  if (chk(hipMalloc(&c->dscal, 4 * sizeof(double)), "hipMalloc")) return bail(VPS_E_NOMEM);
+  if (chk(hipHostMalloc(&c->hscal, 4 * sizeof(double), 0), "hipHostMalloc")) return bail(VPS_E_NOMEM);
+  if (chk(hipEventCreate(&c->ev0), "hipEventCreate") || chk(hipEventCreate(&c->ev1), "hipEventCreate")) return bail(VPS_E_HIP);
+  if (chk(hipStreamSynchronize(c->stream), "hipStreamSynchronize")) return bail(VPS_E_HIP);
   *out = c;
   return VPS_OK;
 }

@@ -743,6 +743,10 @@ struct WaveArgs {
   int v0[3];
   int np[3];
   unsigned npatch;
+  unsigned vec_bytes;  // bytes of one level vector (< 2^32)
+  // exact division by np[0] and np[1] for dividends below 2^32 / divisor:
+  // n / d = umulhi(n, floor(2^32 / d) + 1)
+  unsigned magic_x, magic_y;
   T M[(2 * K - 1) * (2 * K + 1)];    // interior rows of the 2-cell patch mass matrix
   T Kst[(2 * K - 1) * (2 * K + 1)];  // ... and stiffness matrix
   WaveFdm<T, K> f;
@@ -756,11 +760,37 @@ __device__ inline void boundary_column(int lane, int& y, int& x) {
   else { const int r = lane - 2 * P; y = 1 + (r >> 1); x = (r & 1) ? P - 1 : 0; }
 }
 
+// Raw buffer accesses: a wave-uniform descriptor over a whole level vector,
+// a wave-uniform byte offset (SGPR) and a 32-bit per-lane byte offset.
+// Out-of-range offsets read 0 and drop the store (hardware range check).
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+  }
+}
+template <typename T>
+__device__ inline void buf_store(T v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+  } else {
+    typedef unsigned u32x2 __attribute__((vector_size(8)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+  }
+}
+
 // Global accesses are organised so that consecutive lanes touch consecutive
-// x: closure columns and right-hand side columns are read plane by plane,
-// and the new interior is written plane by plane (the last transform of the
-// fast diagonalisation runs along z for that reason; the three 1D transforms
-// of T (x) T (x) T commute).
+// x (this matters more than any other choice measured for this kernel):
+// closure columns and right-hand side columns are read plane by plane (the
+// right-hand side waits in LDS until the residual is formed), and the back
+// transform ends along z so that the new interior is written plane by plane
+// (the three 1D transforms of T (x) T (x) T commute).  One wave per patch,
+// one wave per workgroup.
 template <typename T, int K>
 __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a) {
   constexpr int P = 2 * K + 1, Q = 2 * K - 1, P2 = P * P, Q2 = Q * Q, NB = P2 - Q2;
@@ -777,21 +807,29 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
   if (logical >= a.npatch) return;
   const int lane = threadIdx.x;
   const unsigned npx = (unsigned)a.np[0], npy = (unsigned)a.np[1];
-  const int px = (int)(logical % npx);
-  const int py = (int)((logical / npx) % npy);
-  const int pz = (int)(logical / (npx * npy));
-  const size_t n1 = (size_t)a.n1, n2 = n1 * n1;
-  const size_t base = (size_t)(K * (a.v0[0] + 2 * px - 1)) + n1 * (size_t)(K * (a.v0[1] + 2 * py - 1)) +
+  const unsigned qx = __umulhi(logical, a.magic_x);
+  const unsigned qy = __umulhi(qx, a.magic_y);
+  const int px = (int)(logical - qx * npx);
+  const int py = (int)(qx - qy * npy);
+  const int pz = (int)qy;
+  const unsigned n1 = (unsigned)a.n1;
+  const size_t n2 = (size_t)n1 * n1;
+  const size_t base = (size_t)(K * (a.v0[0] + 2 * px - 1)) + (size_t)n1 * (size_t)(K * (a.v0[1] + 2 * py - 1)) +
                       n2 * (size_t)(K * (a.v0[2] + 2 * pz - 1));
+  const __amdgpu_buffer_rsrc_t ur = make_rsrc(a.u, a.vec_bytes);
+  const __amdgpu_buffer_rsrc_t br = make_rsrc(a.b, a.vec_bytes);
+  const __amdgpu_buffer_rsrc_t lr = make_rsrc(a.ilam, (unsigned)(Q * Q2 * sizeof(T)));
+  const unsigned sbase = (unsigned)(base * sizeof(T));  // patch origin, bytes
+  const unsigned splane = (unsigned)(n2 * sizeof(T));   // one z plane, bytes
 
   // ---- 1. z contraction; right-hand side columns into LDS ----
   if (lane < NB) {
     int y, x;
     boundary_column<K>(lane, y, x);
-    const T* col = a.u + base + n1 * y + x;
+    const unsigned off = (n1 * (unsigned)y + (unsigned)x) * (unsigned)sizeof(T);
     T v[P];
 #pragma unroll
-    for (int z = 0; z < P; ++z) v[z] = col[n2 * z];
+    for (int z = 0; z < P; ++z) v[z] = buf_load<T>(ur, off, sbase + splane * z);
 #pragma unroll
     for (int o = 0; o < Q; ++o) {
       const int j = o + 1;
@@ -799,27 +837,25 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
 #pragma unroll
       for (int z = 0; z < P; ++z) {
         if (z < band_lo(j, K) || z > band_hi(j, K)) continue;
-        zm += a.M[o * P + z] * v[z];
-        zk += a.Kst[o * P + z] * v[z];
+        zm = fma(a.M[o * P + z], v[z], zm);
+        zk = fma(a.Kst[o * P + z], v[z], zk);
       }
       Z[(0 * Q + o) * P2 + y * P + x] = zm;
       Z[(1 * Q + o) * P2 + y * P + x] = zk;
     }
   }
   if (lane < Q2) {
-    const int oy = lane / Q, ox = lane % Q;
-    const int y = 1 + oy, x = 1 + ox;
-    const T* col = a.u + base + n1 * y + x;
-    const T* bcol = a.b + base + n1 * y + x;
-    const T v0 = col[0], v1 = col[n2 * (P - 1)];
+    const int y = 1 + lane / Q, x = 1 + lane % Q;
+    const unsigned off = (n1 * (unsigned)y + (unsigned)x) * (unsigned)sizeof(T);
+    const T v0 = buf_load<T>(ur, off, sbase), v1 = buf_load<T>(ur, off, sbase + splane * (P - 1));
 #pragma unroll
-    for (int o = 0; o < Q; ++o) B[o * Q2 + lane] = bcol[n2 * (o + 1)];
+    for (int o = 0; o < Q; ++o) B[o * Q2 + lane] = buf_load<T>(br, off, sbase + splane * (o + 1));
 #pragma unroll
     for (int o = 0; o < Q; ++o) {
       const int j = o + 1;
       T zm = T(0), zk = T(0);
-      if (band_lo(j, K) == 0) { zm += a.M[o * P] * v0; zk += a.Kst[o * P] * v0; }
-      if (band_hi(j, K) == P - 1) { zm += a.M[o * P + P - 1] * v1; zk += a.Kst[o * P + P - 1] * v1; }
+      if (band_lo(j, K) == 0) { zm = fma(a.M[o * P], v0, zm); zk = fma(a.Kst[o * P], v0, zk); }
+      if (band_hi(j, K) == P - 1) { zm = fma(a.M[o * P + P - 1], v1, zm); zk = fma(a.Kst[o * P + P - 1], v1, zk); }
       Z[(0 * Q + o) * P2 + y * P + x] = zm;
       Z[(1 * Q + o) * P2 + y * P + x] = zk;
     }
@@ -842,8 +878,9 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
 #pragma unroll
       for (int y = 0; y < P; ++y) {
         if (y < band_lo(j, K) || y > band_hi(j, K)) continue;
-        av += a.M[o * P + y] * zm[y];
-        ev += a.Kst[o * P + y] * zm[y] + a.M[o * P + y] * zk[y];
+        av = fma(a.M[o * P + y], zm[y], av);
+        ev = fma(a.Kst[o * P + y], zm[y], ev);
+        ev = fma(a.M[o * P + y], zk[y], ev);
       }
       AE[((0 * Q + oz) * Q + o) * P + x] = av;
       AE[((1 * Q + oz) * Q + o) * P + x] = ev;
@@ -868,7 +905,8 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
 #pragma unroll
       for (int x = 0; x < P; ++x) {
         if (x < band_lo(j, K) || x > band_hi(j, K)) continue;
-        s += a.Kst[o * P + x] * av[x] + a.M[o * P + x] * ev[x];
+        s = fma(a.Kst[o * P + x], av[x], s);
+        s = fma(a.M[o * P + x], ev[x], s);
       }
       r[o] = B[oz * Q2 + oy * Q + o] - s;
     }
@@ -898,10 +936,10 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
     for (int i = 0; i < Q; ++i) v[i] = W1[(i * Q + my) * Q + mx];
     fdm_forward<T, K>(a.f, v, c);
 #pragma unroll
-    for (int j = 0; j < Q; ++j) W0[(j * Q + my) * Q + mx] = c[j] * a.ilam[(j * Q + my) * Q + mx];
+    for (int j = 0; j < Q; ++j)
+      W0[(j * Q + my) * Q + mx] = c[j] * buf_load<T>(lr, (unsigned)(((j * Q + my) * Q + mx) * sizeof(T)), 0u);
   }
   __syncthreads();
-
   // ---- 6. T along x  (lanes (mz, my)) ----
   if (lane < Q2) {
     const int mz = lane / Q, my = lane % Q;
@@ -913,7 +951,6 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
     for (int i = 0; i < Q; ++i) W1[(mz * Q + my) * Q + i] = d[i];
   }
   __syncthreads();
-
   // ---- 7. T along y  (lanes (mz, x)) ----
   if (lane < Q2) {
     const int mz = lane / Q, x = lane % Q;
@@ -925,17 +962,16 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
     for (int i = 0; i < Q; ++i) W0[(mz * Q + i) * Q + x] = d[i];
   }
   __syncthreads();
-
   // ---- 8. T along z, store the new interior plane by plane  (lanes (y, x)) ----
   if (lane < Q2) {
     T c[Q], d[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) c[j] = W0[j * Q2 + lane];
     fdm_backward<T, K>(a.f, c, d);
-    const int oy = lane / Q, ox = lane % Q;
-    T* col = a.u + base + n2 + n1 * (oy + 1) + (ox + 1);
+    const int y = 1 + lane / Q, x = 1 + lane % Q;
+    const unsigned off = (n1 * (unsigned)y + (unsigned)x) * (unsigned)sizeof(T);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) col[n2 * i] = d[i];
+    for (int i = 0; i < Q; ++i) buf_store<T>(d[i], ur, off, sbase + splane * (i + 1));
   }
 }
 

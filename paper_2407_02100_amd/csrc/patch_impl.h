@@ -72,12 +72,23 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
         w.np[e] = a.np[e];
       }
       w.npatch = (unsigned)a.np[0] * (unsigned)a.np[1] * (unsigned)a.np[2];
+      // the patch decomposition divides numbers below npatch by np[0] and np[1]
+      if ((unsigned long long)w.npatch * (unsigned)a.np[0] >= (1ull << 32) ||
+          (unsigned long long)w.npatch * (unsigned)a.np[1] >= (1ull << 32))
+        return hipErrorInvalidValue;
+      const unsigned long long vbytes = (unsigned long long)a.n1 * a.n1 * a.n1 * sizeof(T);
+      if (vbytes >= (1ull << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
+      w.vec_bytes = (unsigned)vbytes;
+      w.magic_x = (unsigned)((1ull << 32) / (unsigned)a.np[0] + 1);
+      w.magic_y = (unsigned)((1ull << 32) / (unsigned)a.np[1] + 1);
       for (int i = 0; i < Q * P; ++i) {
         w.M[i] = a.m.M[0][i];
         w.Kst[i] = a.m.Kst[0][i];
       }
       for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
       for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
+      // one wave per patch, WAVES patches per workgroup; the grid is padded to a
+      // multiple of the XCD count
       // one wave per patch; the grid is padded to a multiple of the XCD count
       const unsigned grid = (w.npatch + kXcd - 1) / kXcd * kXcd;
       patch_wave3_kernel<T, K><<<grid, 64, 0, s>>>(w);

@@ -106,6 +106,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise VpsError(VPS_E_STATE, f"{LIB_PATH} is missing; build it with "
                                         "`python -m paper_2407_02100_amd.build`")
+        # torch ships its own HIP/HSA runtime (same SONAMEs as /opt/rocm's);
+        # importing it first makes libvps bind to that one, so the process
+        # holds a single runtime and torch's stream handles are valid here.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -157,7 +164,7 @@ class Context:
         st = lib().vps_create(ctypes.byref(cfg), stream if stream is not None else _current_stream(),
                               ctypes.byref(h))
         if st != VPS_OK:
-            raise VpsError(st, "vps_create")
+            raise VpsError(st, lib().vps_last_error(None).decode())
         self.h = h
 
     # -- helpers --

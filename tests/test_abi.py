@@ -62,6 +62,18 @@ def test_create_rejects_invalid_configurations(lib, cfg, status):
     assert not h.value
 
 
+def test_binding_loads_a_single_hip_runtime():
+    """libvps must bind to the HIP runtime torch already uses (one runtime per process)."""
+    import subprocess
+    import sys
+    code = ("import paper_2407_02100_amd.vps as v; v.lib(); "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
+
+
 def test_null_arguments_are_rejected(lib):
     from paper_2407_02100_amd import vps
     L = vps.lib()
