@@ -197,12 +197,24 @@ vps_status vps_vcycle_iterate(vps_context* ctx, const double* b, double* u, int 
  * patch's 2^d cells (lexicographic, x fastest), FP32, n_patches x 2^d. */
 vps_status vps_patch_features(vps_context* ctx, int level, float* x_dev);
 
-/* Training targets from exact dense patch operators.  rho8: n x 2^d FP64
- * per-cell coefficients of n patches (device).  Per patch: assemble
+/* Cell coefficients of every patch of a level: rho8[j][c] for the patch's
+ * 2^d cells (lexicographic, x fastest), FP64, n_patches x 2^d (device). */
+vps_status vps_patch_rho8(vps_context* ctx, int level, double* rho8_dev);
+
+/* Features of n arbitrary patches from their cell coefficients:
+ * x[j][c] = log(rho8[j][c] / mean_c rho8[j][c]), FP32, n x 2^d (device). */
+vps_status vps_rho8_features(vps_context* ctx, const double* rho8_dev, long long n, float* x_dev);
+
+/* Training targets from exact dense patch operators (Q2, d = 3).  rho8: n x 8
+ * FP64 per-cell coefficients of n patches (device).  Per patch: assemble
  * A_j(rho), Y = S^T A_j S, solve (Y o Y) d = diag(Y) by Cholesky,
- * c*_m = rhobar Lambda_m d_m.  cstar: n x q^d FP64 (device). */
+ * c*_m = rhobar Lambda_m d_m: the per-mode scaling of the FDM inverse that
+ * minimises ||I - A_j^{1/2} B_j A_j^{1/2}||_F (a reading of the remark that
+ * approximate local solvers are allowed, after eq:main:2).  cstar: n x 27
+ * FP64 (device).  log_target (device, may be NULL): n x 27 FP32 values
+ * log(clamp(c*, 1/4, 4)), the regression target of the MLP. */
 vps_status vps_patch_targets(vps_context* ctx, const double* rho8_dev, long long n,
-                             double* cstar_dev);
+                             double* cstar_dev, float* log_target_dev);
 
 /* MLP n_in -> n_h (tanh) -> n_h (tanh) -> n_out with n_in = 2^d, n_h = 64,
  * n_out = q^d, FP32.  params: flat W1 (n_h x n_in, row-major), b1, W2, b2, W3

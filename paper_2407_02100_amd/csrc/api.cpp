@@ -1013,13 +1013,30 @@ vps_status vps_patch_features(vps_context* c, int level, float* x) {
   return VPS_OK;
 }
 
-vps_status vps_patch_targets(vps_context* c, const double* rho8, long long n, double* cstar) {
+vps_status vps_patch_rho8(vps_context* c, int level, double* rho8) {
+  if (!c || !rho8) return fail(c, VPS_E_ARG, "null argument");
+  if (!level_ok(c, level)) return fail(c, VPS_E_ARG, "invalid level");
+  if (c->cfg.coef == VPS_COEF_CONST || !c->coef_set) return fail(c, VPS_E_STATE, "no cell coefficient set");
+  const Level& L = c->lv[level];
+  VPS_HIP(c, vps::launch_patch_rho8(L.rho64, L.ncell, c->cfg.dim, rho8, c->stream));
+  return VPS_OK;
+}
+
+vps_status vps_rho8_features(vps_context* c, const double* rho8, long long n, float* x) {
+  if (!c || (n > 0 && (!rho8 || !x))) return fail(c, VPS_E_ARG, "null argument");
+  if (n < 0) return fail(c, VPS_E_ARG, "negative count");
+  if (n == 0) return VPS_OK;
+  VPS_HIP(c, vps::launch_rho8_features(rho8, n, c->cfg.dim, x, c->stream));
+  return VPS_OK;
+}
+
+vps_status vps_patch_targets(vps_context* c, const double* rho8, long long n, double* cstar, float* logt) {
   if (!c || (!rho8 && n > 0) || (!cstar && n > 0)) return fail(c, VPS_E_ARG, "null argument");
   if (n < 0) return fail(c, VPS_E_ARG, "negative count");
   if (c->cfg.degree != 2 || c->cfg.dim != 3) return fail(c, VPS_E_UNSUPPORTED, "targets are implemented for Q2 in 3D");
   if (n == 0) return VPS_OK;
   const Level& L = c->lv.back();
-  VPS_HIP(c, vps::launch_patch_targets(rho8, n, L.Mh, L.Kh, L.T1.data(), L.lam.data(), cstar, c->stream));
+  VPS_HIP(c, vps::launch_patch_targets(rho8, n, L.Mh, L.Kh, L.T1.data(), L.lam.data(), cstar, logt, c->stream));
   return VPS_OK;
 }
 

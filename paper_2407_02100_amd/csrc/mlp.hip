@@ -42,6 +42,26 @@ __global__ void __launch_bounds__(kBlock) features_kernel(const double* __restri
   for (int c = 0; c < nc; ++c) x[j * nc + c] = (float)log(r[c] / mean);
 }
 
+__global__ void __launch_bounds__(kBlock) rho8_kernel(const double* __restrict__ rho, int ncell, int dim,
+                                                      long long npatch, double* __restrict__ rho8) {
+  const long long j = blockIdx.x * (long long)kBlock + threadIdx.x;
+  if (j >= npatch) return;
+  int v[3];
+  patch_vertex(j, ncell, dim, v);
+  const int nc = 1 << dim;
+  for (int c = 0; c < nc; ++c) rho8[j * nc + c] = patch_cell_rho(rho, ncell, dim, v, c);
+}
+
+__global__ void __launch_bounds__(kBlock) rho8_features_kernel(const double* __restrict__ rho8, long long n, int nc,
+                                                               float* __restrict__ x) {
+  const long long j = blockIdx.x * (long long)kBlock + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < nc; ++c) s += rho8[j * nc + c];
+  const double mean = s / nc;
+  for (int c = 0; c < nc; ++c) x[j * nc + c] = (float)log(rho8[j * nc + c] / mean);
+}
+
 // ---- network evaluation, one thread per sample, parameters in LDS ----
 struct Net {
   const float* W1;
@@ -274,7 +294,7 @@ struct TargetArgs {
 };
 
 __global__ void __launch_bounds__(64) targets_kernel(const TargetArgs a, const double* __restrict__ rho8,
-                                                     double* __restrict__ cstar) {
+                                                     double* __restrict__ cstar, float* __restrict__ logt) {
   constexpr int Q = 3, N = 27;
   __shared__ double A[N * N];
   __shared__ double S[N * N];
@@ -354,7 +374,9 @@ __global__ void __launch_bounds__(64) targets_kernel(const TargetArgs a, const d
   __syncthreads();
   if (lane < N) {
     const int mx = lane % Q, my = (lane / Q) % Q, mz = lane / (Q * Q);
-    cstar[j * N + lane] = rbar * (a.lam[mx] + a.lam[my] + a.lam[mz]) * sol[lane];
+    const double c = rbar * (a.lam[mx] + a.lam[my] + a.lam[mz]) * sol[lane];
+    cstar[j * N + lane] = c;
+    if (logt) logt[j * N + lane] = (float)log(fmin(fmax(c, 0.25), 4.0));
   }
 }
 
@@ -404,9 +426,22 @@ hipError_t launch_patch_features(const double* rho, int ncell, int dim, float* x
   return hipGetLastError();
 }
 
+hipError_t launch_patch_rho8(const double* rho, int ncell, int dim, double* rho8, hipStream_t s) {
+  long long np = 1;
+  for (int e = 0; e < dim; ++e) np *= (ncell - 1);
+  if (np <= 0) return hipSuccess;
+  rho8_kernel<<<blocks_for(np), kBlock, 0, s>>>(rho, ncell, dim, np, rho8);
+  return hipGetLastError();
+}
+
+hipError_t launch_rho8_features(const double* rho8, long long n, int dim, float* x, hipStream_t s) {
+  rho8_features_kernel<<<blocks_for(n), kBlock, 0, s>>>(rho8, n, 1 << dim, x);
+  return hipGetLastError();
+}
+
 hipError_t launch_patch_targets(const double* rho8, long long n, const std::vector<double>* Mh,
                                 const std::vector<double>* Kh, const double* T1, const double* lam, double* cstar,
-                                hipStream_t s) {
+                                float* log_target, hipStream_t s) {
   constexpr int Q = 3, P = 5;
   TargetArgs a;
   for (int h = 0; h < 2; ++h)
@@ -419,7 +454,8 @@ hipError_t launch_patch_targets(const double* rho8, long long n, const std::vect
   for (int i = 0; i < Q; ++i) a.lam[i] = lam[i];
   for (long long first = 0; first < n; first += 1 << 30) {
     const long long cnt = (n - first < (1LL << 30)) ? n - first : (1LL << 30);
-    targets_kernel<<<(unsigned)cnt, 64, 0, s>>>(a, rho8 + first * 8, cstar + first * 27);
+    targets_kernel<<<(unsigned)cnt, 64, 0, s>>>(a, rho8 + first * 8, cstar + first * 27,
+                                                 log_target ? log_target + first * 27 : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

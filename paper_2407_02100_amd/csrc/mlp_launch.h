@@ -31,11 +31,13 @@ hipError_t mlp_ensure(MlpWork* w);
 void mlp_free(MlpWork* w);
 
 hipError_t launch_patch_features(const double* rho, int ncell, int dim, float* x, hipStream_t s);
+hipError_t launch_patch_rho8(const double* rho, int ncell, int dim, double* rho8, hipStream_t s);
+hipError_t launch_rho8_features(const double* rho8, long long n, int dim, float* x, hipStream_t s);
 
 // Exact targets for Q2 patches in 3D (see vps_patch_targets).
 hipError_t launch_patch_targets(const double* rho8, long long n, const std::vector<double>* Mh,
                                 const std::vector<double>* Kh, const double* T1, const double* lam, double* cstar,
-                                hipStream_t s);
+                                float* log_target, hipStream_t s);
 
 hipError_t launch_mlp_forward(const float* params, const float* x, long long n, int nin, int nout, float* y,
                               float* act, hipStream_t s);

@@ -83,7 +83,9 @@ SIGNATURES = {
     "vps_solve": (_i, [_vp, _vp, _vp, _d, _i, ctypes.POINTER(vps_solve_info)]),
     "vps_vcycle_iterate": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d)]),
     "vps_patch_features": (_i, [_vp, _i, _vp]),
-    "vps_patch_targets": (_i, [_vp, _vp, _ll, _vp]),
+    "vps_patch_rho8": (_i, [_vp, _i, _vp]),
+    "vps_rho8_features": (_i, [_vp, _vp, _ll, _vp]),
+    "vps_patch_targets": (_i, [_vp, _vp, _ll, _vp, _vp]),
     "vps_mlp_forward": (_i, [_vp, _vp, _vp, _ll, _vp, _vp]),
     "vps_mlp_loss_grad": (_i, [_vp, _vp, _vp, _ll, _vp, _vp]),
     "vps_mlp_backward": (_i, [_vp, _vp, _vp, _vp, _vp, _ll, _vp]),
@@ -260,8 +262,15 @@ class Context:
     def patch_features(self, level, x):
         self._check(lib().vps_patch_features(self.h, level, _ptr(x)), "vps_patch_features")
 
-    def patch_targets(self, rho8, cstar):
-        self._check(lib().vps_patch_targets(self.h, _ptr(rho8), rho8.shape[0], _ptr(cstar)), "vps_patch_targets")
+    def patch_rho8(self, level, rho8):
+        self._check(lib().vps_patch_rho8(self.h, level, _ptr(rho8)), "vps_patch_rho8")
+
+    def rho8_features(self, rho8, x):
+        self._check(lib().vps_rho8_features(self.h, _ptr(rho8), rho8.shape[0], _ptr(x)), "vps_rho8_features")
+
+    def patch_targets(self, rho8, cstar, log_target=None):
+        self._check(lib().vps_patch_targets(self.h, _ptr(rho8), rho8.shape[0], _ptr(cstar), _ptr(log_target)),
+                    "vps_patch_targets")
 
     def mlp_forward(self, params, x, y, act=None):
         self._check(lib().vps_mlp_forward(self.h, _ptr(params), _ptr(x), x.shape[0], _ptr(y), _ptr(act)),
@@ -315,7 +324,8 @@ def _method_alias(name):
 
 for _n in ("destroy", "set_stream", "level_nodes", "level_cells", "level_patches", "set_coefficient",
            "set_patch_scaling", "apply", "residual", "restrict", "prolongate_add", "coarse_solve",
-           "smooth_color", "smooth", "vcycle", "solve", "vcycle_iterate", "patch_features", "patch_targets",
+           "smooth_color", "smooth", "vcycle", "solve", "vcycle_iterate", "patch_features", "patch_rho8",
+           "rho8_features", "patch_targets",
            "mlp_forward", "mlp_loss_grad", "mlp_backward", "mlp_adam", "mlp_infer_patches", "timing_enable",
            "timing_get", "sync"):
     globals()["vps_" + _n] = _method_alias(_n)

@@ -156,3 +156,27 @@ def test_infer_patches_and_fallback(vps):
         u = dev(u0)
         ctx.smooth(0, u, dev(b), sweeps=1)
         assert rel(host(u), smoother.sweep_alg3(A, b, u0, P, S2)) <= 1e-12
+
+
+def test_learned_scaling_gain_on_held_out_rough_field(vps):
+    """Train the MLP with the library's kernels, then compare with plain rhobar-FDM on a held-out field.
+
+    32^3 Q2, 4 levels, rho = exp(GRF) with correlation length 1/8 (4 cells): the
+    plain smoother overshoots (lambda_max(B_j A_j) > 2 on many coarse patches)
+    and the stationary V-cycle diverges; the learned scaling restores a
+    contractive V-cycle (CG, which tolerates the overshoot, needs no more
+    iterations with it).
+    """
+    say("learned gain")
+    from paper_2407_02100_amd import learned
+    X, T, C, R = learned.training_set([1000, 1001, 1002], n_cells=32, levels=4, total=40_000)
+    base = learned.baseline_loss(T)
+    p, hist = learned.train(X, T, epochs=15)
+    assert hist["val_loss"][-1] < 0.1 * base
+    res = learned.compare(p, n_cells=32, levels=4, rho_seed=4, rhs_seed=4, maxit=200)
+    plain, lrn = res["mean"], res["learned"]
+    say("plain", plain["factor"], plain["iterations"], "learned", lrn["factor"], lrn["iterations"])
+    assert all(f == 0 for f in lrn["fallback_per_level"])
+    assert lrn["status"] == 0 and lrn["rel_residual_true"] <= 1e-10
+    assert lrn["factor"] < 0.9 < plain["factor"]
+    assert lrn["iterations"] <= plain["iterations"]
