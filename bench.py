@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "patch_sweep_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_02100_amd", "csrc", f) for f in ("kernels.h", "patch_impl.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_02100_amd", "csrc", f) for f in ("patch_wave.h", "patch_impl.h")]
 
 
 def kernel_source_hash() -> str:
@@ -118,6 +118,55 @@ def cpu_baseline(dim: int, degree: int):
 
 
 # ---------------------------------------------------------------------------
+# Other workloads (outside the timed region): time to 1e-10 of the plain,
+# mixed-precision and learned forms on the same GPU.
+
+def _solve(torch, vps, vi, name, vcycle=None, reps=3):
+    w = vi.WORKLOADS[name]
+    dim, k, N = w["dim"], w["degree"], w["n_cells"]
+    b = torch.from_numpy(vi.seeded_vector(dim, k, N, w["rhs_seed"])).to("cuda")
+    x = torch.empty_like(b)
+    with vps.Context(dim, k, N, w["levels"], w["pre"], w["post"], vcycle_dtype=vcycle or w["vcycle"]) as ctx:
+        ctx.solve(b, x, rtol=1e-10, maxit=200)
+        infos = [ctx.solve(b, x, rtol=1e-10, maxit=200) for _ in range(reps)]
+    t = sorted(i["seconds"] for i in infos)[len(infos) // 2]
+    return {"solve_s": t, "iterations": infos[-1]["iterations"],
+            "rel_residual_true": max(i["rel_residual_true"] for i in infos)}, x
+
+
+def run_extras(torch, vps, vi):
+    out = {}
+    print("[bench] small workloads", file=sys.stderr, flush=True)
+    for name in ("poisson2d_q2_n32", "poisson3d_q4_n32"):
+        out[name], _ = _solve(torch, vps, vi, name)
+    print("[bench] mixed precision, 3D Q3 64^3", file=sys.stderr, flush=True)
+    r64, x64 = _solve(torch, vps, vi, "poisson3d_q3_n64", vcycle="f64")
+    r32, x32 = _solve(torch, vps, vi, "poisson3d_q3_n64", vcycle="f32")
+    diff = float(torch.linalg.vector_norm(x32 - x64) / torch.linalg.vector_norm(x64))
+    out["poisson3d_q3_n64"] = {"plain_f64": r64, "f32_vcycle": r32,
+                               "speedup_f32_vs_f64": r64["solve_s"] / r32["solve_s"],
+                               "rel_diff_solution_f32_vs_f64": diff}
+    print("[bench] learned scaling, 3D Q2 64^3", file=sys.stderr, flush=True)
+    from paper_2407_02100_amd import learned
+    res = {}
+    for tag, cl in (("corr_len_1/8", 1.0 / 8.0), ("corr_len_1/16", 1.0 / 16.0)):
+        t0 = time.perf_counter()
+        X, T, C, R = learned.training_set([1000, 1001, 1002, 1003], n_cells=64, levels=5, total=200_000,
+                                          corr_len=cl)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p, hist = learned.train(X, T, epochs=30)
+        cmp = learned.compare(p, n_cells=64, levels=5, rho_seed=4, rhs_seed=4, corr_len=cl)
+        for v in cmp.values():
+            v.pop("residual_history", None)
+        res[tag] = {"targets_and_dataset_s": t1 - t0, "train_s": hist["seconds"], "train_samples": hist["train_samples"],
+                    "val_loss_plain": learned.baseline_loss(T[: hist["val_samples"]]),
+                    "val_loss_learned": hist["val_loss"][-1], "plain": cmp["mean"], "learned": cmp["learned"],
+                    "speedup_learned_vs_plain": (cmp["mean"]["seconds"] / cmp["learned"]["seconds"]
+                                                 if cmp["mean"]["status"] == 0 else None)}
+    out["varcoef3d_q2_n64"] = res
+    return out
+
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -127,6 +176,8 @@ def main():
     ap.add_argument("--workload", default="poisson3d_q4_n128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64-reference", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (mixed Q3, learned Q2, small problems)")
     ap.add_argument("--oracle-child", nargs=3, type=int, metavar=("N", "K", "D"))
     args = ap.parse_args()
 
@@ -224,6 +275,8 @@ def main():
                "smoother_dof_per_s": n * t64["smooth_sweeps"][L] / t64["smooth_s"][L],
                "smoother_gbs": sweep_bytes(dim, k, N, 8) * t64["smooth_sweeps"][L] / t64["smooth_s"][L] / 1e9}
 
+    extras = {} if args.no_extras else run_extras(torch, vps, vi)
+
     solve_s = sum(i["seconds"] for i in infos) / len(infos)
     total_phases = (sum(tim["smooth_s"]) + sum(tim["residual_s"]) + sum(tim["restrict_s"]) +
                     sum(tim["prolong_s"]) + tim["coarse_s"] + tim["cg_operator_s"] + tim["cg_vector_s"])
@@ -261,10 +314,11 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "patch_color_kernel (one color of the smoother, finest level)",
+                     "kernel": "patch_wave3_kernel (one color of the smoother, finest level)",
                      "avg_launch_us": per_launch_s * 1e6, "bytes_per_launch": bytes_sweep / 2 ** dim,
                      "measured_copy_gbs": copy_gbs},
         "cpu_baseline": cpu,
+        "other_workloads": extras,
     }
     print(json.dumps(out))
     return 0

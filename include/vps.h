@@ -79,6 +79,12 @@ typedef struct {
   int patches_per_block; /* 0 = automatic (3D rho = 1: one patch per wavefront);
                             1, 2, 4 = batches of that many patches along x per
                             256-thread workgroup */
+  int stream_min_cells;  /* 3D: the operator and the residual (rho = 1) and the
+                            grid transfers use the plane-streaming kernels on
+                            levels with at least this many cells per direction
+                            (for a transfer: on its coarse level), single-pass
+                            tile kernels below; 0 = default (32), 1 = always;
+                            must be >= 0 */
 } vps_config;
 
 typedef struct {

@@ -50,3 +50,42 @@ def prolongation(dim: int, k: int, n_coarse: int) -> sp.csr_matrix:
     out = (Df @ P @ Dc).tocsr()
     out.eliminate_zeros()
     return out
+
+
+def _along(mat, X, e, dim):
+    """Apply a 1D matrix along direction e of a nodal array (e = 0 is x, the last numpy axis)."""
+    ax = dim - 1 - e
+    Xm = np.moveaxis(X, ax, 0)
+    sh = Xm.shape
+    Y = (mat @ Xm.reshape(sh[0], -1)).reshape((mat.shape[0],) + sh[1:])
+    return np.moveaxis(Y, 0, ax)
+
+
+def restrict_kron(dim: int, k: int, n_coarse: int, r_fine: np.ndarray) -> np.ndarray:
+    """P^T r_fine without forming P: the transpose of the 1D prolongation along each axis.
+
+    Same result as ``prolongation(dim, k, n_coarse).T @ r_fine`` (the tensor
+    product of the 1D transposes, with the Dirichlet entries of both levels
+    masked), for grids too large for the sparse Kronecker product.
+    """
+    P1t = sp.csr_matrix(prolongation_1d(k, n_coarse).T)
+    nf = k * 2 * n_coarse + 1
+    free_f = free_mask_flat(dim, k, 2 * n_coarse)
+    X = np.where(free_f, np.asarray(r_fine, dtype=np.float64), 0.0).reshape((nf,) * dim)
+    for e in range(dim):
+        X = _along(P1t, X, e, dim)
+    out = X.reshape(-1)
+    out[~free_mask_flat(dim, k, n_coarse)] = 0.0
+    return out
+
+
+def prolong_kron(dim: int, k: int, n_coarse: int, e_coarse: np.ndarray) -> np.ndarray:
+    """P e_coarse without forming P: the 1D prolongation along each axis, Dirichlet entries masked."""
+    P1 = sp.csr_matrix(prolongation_1d(k, n_coarse))
+    nc = k * n_coarse + 1
+    X = np.where(free_mask_flat(dim, k, n_coarse), np.asarray(e_coarse, dtype=np.float64), 0.0).reshape((nc,) * dim)
+    for e in range(dim):
+        X = _along(P1, X, e, dim)
+    out = X.reshape(-1)
+    out[~free_mask_flat(dim, k, 2 * n_coarse)] = 0.0
+    return out

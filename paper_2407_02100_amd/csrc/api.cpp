@@ -40,6 +40,10 @@ struct Level {
   Mat restrictG;            // transfer tile: this level -> level-1
   Mat prolongG;             // transfer tile: level-1 -> this level
   Mat Mc, Kc;               // cell matrices (h-scaled)
+  // plane-streaming kernels (3D): period rows of the 1D operators and z cell tables
+  Mat sG0, sG1, sZ0, sZ1;   // operator: mass / stiffness, K x (2K+1) and (K+1) x (K+1)
+  Mat rG, rZ;               // restriction to level-1: K x (4K+1) and (K+1) x (2K+1)
+  Mat pG;                   // prolongation from level-1: 2K x (K+1) (period rows and z cell table)
 };
 
 enum Phase { PH_SMOOTH, PH_RESIDUAL, PH_RESTRICT, PH_PROLONG, PH_COARSE, PH_CG_OP, PH_CG_VEC };
@@ -130,6 +134,23 @@ template <typename F>
 hipError_t dispatch_tkd(vps_dtype t, int k, int d, F&& f) {
   if (t == VPS_F64) return dispatch_kd<double>(k, d, f);
   return dispatch_kd<float>(k, d, f);
+}
+
+template <typename T, typename F>
+hipError_t dispatch_k(int k, F& f) {
+  switch (k) {
+    case 1: return f.template operator()<T, 1>();
+    case 2: return f.template operator()<T, 2>();
+    case 3: return f.template operator()<T, 3>();
+    case 4: return f.template operator()<T, 4>();
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename F>
+hipError_t dispatch_tk(vps_dtype t, int k, F&& f) {
+  if (t == VPS_F64) return dispatch_k<double>(k, f);
+  return dispatch_k<float>(k, f);
 }
 
 hipError_t timer_flush(vps_context* c);
@@ -285,6 +306,37 @@ void build_level(Level& L, int k, int d, int ncell) {
     L.Mc[i] = L.h * Mr[i];
     L.Kc[i] = Kr[i] / L.h;
   }
+  // streaming tables: rows k..2k-1 of the 1D operators of a two-cell mesh (the
+  // vertex row and the interior rows of a cell, translation invariant), and the
+  // 1D prolongation block of coarse cell 1 of a two-cell coarse mesh
+  {
+    Mat M, K;
+    vps::assemble_1d(k, 2, L.h, &M, &K);
+    const int n = 2 * k + 1, W = 2 * k + 1;
+    L.sG0.assign(k * W, 0.0);
+    L.sG1.assign(k * W, 0.0);
+    for (int j = 0; j < k; ++j)
+      for (int i = 0; i < W; ++i) {
+        L.sG0[j * W + i] = M[(k + j) * n + i];
+        L.sG1[j * W + i] = K[(k + j) * n + i];
+      }
+    L.sZ0 = L.Mc;
+    L.sZ1 = L.Kc;
+  }
+  {
+    Mat P1;
+    vps::prolongation_1d(k, 2, &P1);
+    const int ncn = 2 * k + 1, W = 4 * k + 1, ZW = 2 * k + 1;
+    L.rG.assign(k * W, 0.0);
+    for (int j = 0; j < k; ++j)
+      for (int i = 0; i < W; ++i) L.rG[j * W + i] = P1[(size_t)i * ncn + k + j];
+    L.rZ.assign((k + 1) * ZW, 0.0);
+    for (int i = 0; i <= k; ++i)
+      for (int l = 0; l < 2 * k; ++l) L.rZ[i * ZW + l] = P1[(size_t)l * ncn + i];
+    L.pG.assign(2 * k * (k + 1), 0.0);
+    for (int j = 0; j < 2 * k; ++j)
+      for (int i = 0; i <= k; ++i) L.pG[j * (k + 1) + i] = P1[(size_t)j * ncn + i];
+  }
 }
 
 template <typename T>
@@ -298,6 +350,9 @@ hipError_t upload(const std::vector<double>& src, void** dst, hipStream_t s) {
 }
 
 bool level_ok(const vps_context* c, int l) { return c && l >= 0 && l < (int)c->lv.size(); }
+
+// cells per direction from which the plane-streaming kernels are used
+int stream_min(const vps_context* c) { return c->cfg.stream_min_cells > 0 ? c->cfg.stream_min_cells : 32; }
 
 vps_dtype vdt(const vps_context* c) { return (vps_dtype)c->cfg.vcycle_dtype; }
 
@@ -350,6 +405,10 @@ hipError_t do_smooth(vps_context* c, int l, void* u, const void* b, vps_dtype t,
 hipError_t do_operator(vps_context* c, int l, const void* u, const void* b, void* out, vps_dtype t) {
   const Level& L = c->lv[l];
   const int k = c->cfg.degree, d = c->cfg.dim;
+  if (c->cfg.coef == VPS_COEF_CONST && d == 3 && L.ncell >= stream_min(c)) {
+    vps::StreamLaunch S{u, b, out, L.n1, L.n1, L.ncell, L.sG0.data(), L.sG1.data(), L.sZ0.data(), L.sZ1.data()};
+    return dispatch_tk(t, k, [&]<typename TT, int K>() { return vps::launch_stream_operator<TT, K>(S, c->stream); });
+  }
   if (c->cfg.coef == VPS_COEF_CONST) {
     vps::TileLaunch T{};
     T.in = u;
@@ -377,6 +436,12 @@ hipError_t do_operator(vps_context* c, int l, const void* u, const void* b, void
 
 hipError_t do_restrict(vps_context* c, int l, const void* rf, void* rc, vps_dtype t) {
   const int k = c->cfg.degree, d = c->cfg.dim;
+  if (d == 3 && c->lv[l - 1].ncell >= stream_min(c)) {
+    const Level& L = c->lv[l];
+    vps::StreamLaunch S{rf, nullptr, rc, L.n1, c->lv[l - 1].n1, c->lv[l - 1].ncell, L.rG.data(), nullptr,
+                        L.rZ.data(), nullptr};
+    return dispatch_tk(t, k, [&]<typename TT, int K>() { return vps::launch_stream_restrict<TT, K>(S, c->stream); });
+  }
   vps::TileLaunch T{};
   T.in = rf;
   T.out = rc;
@@ -390,6 +455,12 @@ hipError_t do_restrict(vps_context* c, int l, const void* rf, void* rc, vps_dtyp
 
 hipError_t do_prolong(vps_context* c, int l, const void* ec, void* uf, vps_dtype t) {
   const int k = c->cfg.degree, d = c->cfg.dim;
+  if (d == 3 && c->lv[l - 1].ncell >= stream_min(c)) {
+    const Level& L = c->lv[l];
+    vps::StreamLaunch S{ec, nullptr, uf, c->lv[l - 1].n1, L.n1, c->lv[l - 1].ncell, L.pG.data(), nullptr,
+                        L.pG.data(), nullptr};
+    return dispatch_tk(t, k, [&]<typename TT, int K>() { return vps::launch_stream_prolong<TT, K>(S, c->stream); });
+  }
   vps::TileLaunch T{};
   T.in = ec;
   T.out = uf;
@@ -555,6 +626,7 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.vcycle_dtype != VPS_F64 && C.vcycle_dtype != VPS_F32) return VPS_E_ARG;
   if (C.coef < VPS_COEF_CONST || C.coef > VPS_COEF_CELL_LEARNED) return VPS_E_ARG;
   if (C.patches_per_block != 0 && !vps::valid_patches_per_block(C.patches_per_block)) return VPS_E_UNSUPPORTED;
+  if (C.stream_min_cells < 0) return VPS_E_ARG;
   // every node index must fit in int on the kernels' inner indexing
   const double nodes = std::pow((double)(C.degree * C.n_cells + 1), C.dim);
   if (nodes > 2.0e9) return VPS_E_UNSUPPORTED;

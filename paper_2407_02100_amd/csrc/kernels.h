@@ -13,6 +13,8 @@
 namespace vps {
 
 constexpr int kBlock = 256;
+// XCDs of the MI355X: workgroup ids are dealt round-robin over them, and each has its own L2.
+constexpr int kXcd = 8;
 
 // ---------------------------------------------------------------------------
 // 1D band structure.  Nodes are numbered so that cell boundaries sit at
@@ -635,343 +637,6 @@ __global__ void __launch_bounds__(kBlock) tile_kernel(const TileArgs<T, KIND, K,
       }
       a.out[g] = v;
     }
-  }
-}
-
-}  // namespace vps
-
-namespace vps {
-
-// ---------------------------------------------------------------------------
-// Patch smoother, 3D, constant coefficient: one patch at a time per wavefront.
-//
-// With the exact local solver the update of Algorithm 4,
-//   u_int <- ubar_int + A_j^{-1} (b_j - Abar_j ubar),
-// equals A_j^{-1} (b_j - A_{j,Gamma} ubar_Gamma), because the interior rows
-// of Abar_j split into A_j (interior columns) and A_{j,Gamma} (patch boundary
-// columns).  The kernel therefore evaluates the local residual of the
-// closure with the interior values taken as zero, applies the fast
-// diagonalisation and stores the result as the new interior.
-//
-// Fast diagonalisation in even/odd form: the 1D patch problem is symmetric
-// under reversal of the node order, so each eigenvector is symmetric (K of
-// them) or antisymmetric (K-1).  T^T v then needs the folded sums/differences
-// of v and the K x K and (K-1) x (K-1) blocks Te, To only; the modes are kept
-// in the internal order [symmetric..., antisymmetric...] throughout, and the
-// reciprocal eigenvalue sums 1/(lam_x + lam_y + lam_z) come from a per-level
-// table in that order.
-//
-// Lanes of one wave64 per patch:
-//   1. z contraction of the closure columns (y, x): boundary columns carry
-//      2K+1 values, interior columns only their two end values;
-//   2. y contraction of the (z-out, x) lines;
-//   3. x contraction of the (z-out, y-out) lines, local residual, T^T along x;
-//   4. T^T along y;  5. T^T along z, 1/Lambda, T along z;  6. T along y;
-//   7. T along x and store.
-// A wave walks through several patches of the color and loads the next
-// patch's closure columns and right-hand side rows while it computes the
-// current one.  Waves are mapped so that each of the 8 XCDs owns one
-// contiguous slab of the color's patches (lexicographic order), which keeps
-// the closures that neighbouring patches share inside one L2.
-
-constexpr int kXcd = 8;
-
-template <typename T, int K>
-struct WaveFdm {
-  T Te[K * K];              // Te[i*K + j]: component i (0..K-1) of symmetric mode j
-  T To[(K - 1) * (K - 1)];  // To[i*(K-1) + j]: component i (0..K-2) of antisymmetric mode j
-};
-
-template <typename T, int K>
-__device__ inline void fdm_forward(const WaveFdm<T, K>& f, const T (&v)[2 * K - 1], T (&out)[2 * K - 1]) {
-  constexpr int Q = 2 * K - 1, M = K - 1;  // M = index of the middle node
-  T e[K], o[K - 1];
-#pragma unroll
-  for (int i = 0; i < M; ++i) {
-    e[i] = v[i] + v[Q - 1 - i];
-    o[i] = v[i] - v[Q - 1 - i];
-  }
-  e[M] = v[M];
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    T s = T(0);
-#pragma unroll
-    for (int i = 0; i < K; ++i) s += f.Te[i * K + j] * e[i];
-    out[j] = s;
-  }
-#pragma unroll
-  for (int j = 0; j < K - 1; ++j) {
-    T s = T(0);
-#pragma unroll
-    for (int i = 0; i < K - 1; ++i) s += f.To[i * (K - 1) + j] * o[i];
-    out[K + j] = s;
-  }
-}
-
-template <typename T, int K>
-__device__ inline void fdm_backward(const WaveFdm<T, K>& f, const T (&c)[2 * K - 1], T (&out)[2 * K - 1]) {
-  constexpr int Q = 2 * K - 1, M = K - 1;
-  T ce[K], co[K - 1];
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    T s = T(0);
-#pragma unroll
-    for (int j = 0; j < K; ++j) s += f.Te[i * K + j] * c[j];
-    ce[i] = s;
-  }
-#pragma unroll
-  for (int i = 0; i < K - 1; ++i) {
-    T s = T(0);
-#pragma unroll
-    for (int j = 0; j < K - 1; ++j) s += f.To[i * (K - 1) + j] * c[K + j];
-    co[i] = s;
-  }
-#pragma unroll
-  for (int i = 0; i < M; ++i) {
-    out[i] = ce[i] + co[i];
-    out[Q - 1 - i] = ce[i] - co[i];
-  }
-  out[M] = ce[M];
-}
-
-template <typename T, int K>
-struct WaveArgs {
-  T* __restrict__ u;
-  const T* __restrict__ b;
-  const T* __restrict__ ilam;  // Q^3 reciprocal eigenvalue sums, internal mode order, [mz][my][mx]
-  int n1;
-  int v0[3];
-  int np[3];
-  unsigned npatch;
-  unsigned vec_bytes;  // bytes of one level vector (< 2^32)
-  // exact division by np[0] and np[1] for dividends below 2^32 / divisor:
-  // n / d = umulhi(n, floor(2^32 / d) + 1)
-  unsigned magic_x, magic_y;
-  T M[(2 * K - 1) * (2 * K + 1)];    // interior rows of the 2-cell patch mass matrix
-  T Kst[(2 * K - 1) * (2 * K + 1)];  // ... and stiffness matrix
-  WaveFdm<T, K> f;
-};
-
-template <int K>
-__device__ inline void boundary_column(int lane, int& y, int& x) {
-  constexpr int P = 2 * K + 1;
-  if (lane < P) { y = 0; x = lane; }
-  else if (lane < 2 * P) { y = P - 1; x = lane - P; }
-  else { const int r = lane - 2 * P; y = 1 + (r >> 1); x = (r & 1) ? P - 1 : 0; }
-}
-
-// Raw buffer accesses: a wave-uniform descriptor over a whole level vector,
-// a wave-uniform byte offset (SGPR) and a 32-bit per-lane byte offset.
-// Out-of-range offsets read 0 and drop the store (hardware range check).
-__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
-}
-template <typename T>
-__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-  if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-  } else {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-  }
-}
-template <typename T>
-__device__ inline void buf_store(T v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-  if constexpr (sizeof(T) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
-  } else {
-    typedef unsigned u32x2 __attribute__((vector_size(8)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
-  }
-}
-
-// Global accesses are organised so that consecutive lanes touch consecutive
-// x (this matters more than any other choice measured for this kernel):
-// closure columns and right-hand side columns are read plane by plane (the
-// right-hand side waits in LDS until the residual is formed), and the back
-// transform ends along z so that the new interior is written plane by plane
-// (the three 1D transforms of T (x) T (x) T commute).  One wave per patch,
-// one wave per workgroup.
-template <typename T, int K>
-__global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a) {
-  constexpr int P = 2 * K + 1, Q = 2 * K - 1, P2 = P * P, Q2 = Q * Q, NB = P2 - Q2;
-  __shared__ T Z[2 * Q * P2];      // [t][oz][y][x] after the z contraction; later the FDM buffers
-  __shared__ T AE[2 * Q * Q * P];  // [t][oz][oy][x] after the y contraction
-  __shared__ T B[Q * Q2];          // right-hand side of the interior, [oz][oy][ox]
-  T* W0 = Z;
-  T* W1 = Z + Q * Q2;
-  static_assert(2 * Q * Q2 <= 2 * Q * P2, "FDM buffers must fit in Z");
-
-  const unsigned h = blockIdx.x;
-  const unsigned per = gridDim.x / kXcd;
-  const unsigned logical = (h % kXcd) * per + h / kXcd;
-  if (logical >= a.npatch) return;
-  const int lane = threadIdx.x;
-  const unsigned npx = (unsigned)a.np[0], npy = (unsigned)a.np[1];
-  const unsigned qx = __umulhi(logical, a.magic_x);
-  const unsigned qy = __umulhi(qx, a.magic_y);
-  const int px = (int)(logical - qx * npx);
-  const int py = (int)(qx - qy * npy);
-  const int pz = (int)qy;
-  const unsigned n1 = (unsigned)a.n1;
-  const size_t n2 = (size_t)n1 * n1;
-  const size_t base = (size_t)(K * (a.v0[0] + 2 * px - 1)) + (size_t)n1 * (size_t)(K * (a.v0[1] + 2 * py - 1)) +
-                      n2 * (size_t)(K * (a.v0[2] + 2 * pz - 1));
-  const __amdgpu_buffer_rsrc_t ur = make_rsrc(a.u, a.vec_bytes);
-  const __amdgpu_buffer_rsrc_t br = make_rsrc(a.b, a.vec_bytes);
-  const __amdgpu_buffer_rsrc_t lr = make_rsrc(a.ilam, (unsigned)(Q * Q2 * sizeof(T)));
-  const unsigned sbase = (unsigned)(base * sizeof(T));  // patch origin, bytes
-  const unsigned splane = (unsigned)(n2 * sizeof(T));   // one z plane, bytes
-
-  // ---- 1. z contraction; right-hand side columns into LDS ----
-  if (lane < NB) {
-    int y, x;
-    boundary_column<K>(lane, y, x);
-    const unsigned off = (n1 * (unsigned)y + (unsigned)x) * (unsigned)sizeof(T);
-    T v[P];
-#pragma unroll
-    for (int z = 0; z < P; ++z) v[z] = buf_load<T>(ur, off, sbase + splane * z);
-#pragma unroll
-    for (int o = 0; o < Q; ++o) {
-      const int j = o + 1;
-      T zm = T(0), zk = T(0);
-#pragma unroll
-      for (int z = 0; z < P; ++z) {
-        if (z < band_lo(j, K) || z > band_hi(j, K)) continue;
-        zm = fma(a.M[o * P + z], v[z], zm);
-        zk = fma(a.Kst[o * P + z], v[z], zk);
-      }
-      Z[(0 * Q + o) * P2 + y * P + x] = zm;
-      Z[(1 * Q + o) * P2 + y * P + x] = zk;
-    }
-  }
-  if (lane < Q2) {
-    const int y = 1 + lane / Q, x = 1 + lane % Q;
-    const unsigned off = (n1 * (unsigned)y + (unsigned)x) * (unsigned)sizeof(T);
-    const T v0 = buf_load<T>(ur, off, sbase), v1 = buf_load<T>(ur, off, sbase + splane * (P - 1));
-#pragma unroll
-    for (int o = 0; o < Q; ++o) B[o * Q2 + lane] = buf_load<T>(br, off, sbase + splane * (o + 1));
-#pragma unroll
-    for (int o = 0; o < Q; ++o) {
-      const int j = o + 1;
-      T zm = T(0), zk = T(0);
-      if (band_lo(j, K) == 0) { zm = fma(a.M[o * P], v0, zm); zk = fma(a.Kst[o * P], v0, zk); }
-      if (band_hi(j, K) == P - 1) { zm = fma(a.M[o * P + P - 1], v1, zm); zk = fma(a.Kst[o * P + P - 1], v1, zk); }
-      Z[(0 * Q + o) * P2 + y * P + x] = zm;
-      Z[(1 * Q + o) * P2 + y * P + x] = zk;
-    }
-  }
-  __syncthreads();
-
-  // ---- 2. y contraction: A = M_y Zm, E = K_y Zm + M_y Zk ----
-  if (lane < Q * P) {
-    const int oz = lane / P, x = lane % P;
-    T zm[P], zk[P];
-#pragma unroll
-    for (int y = 0; y < P; ++y) {
-      zm[y] = Z[(0 * Q + oz) * P2 + y * P + x];
-      zk[y] = Z[(1 * Q + oz) * P2 + y * P + x];
-    }
-#pragma unroll
-    for (int o = 0; o < Q; ++o) {
-      const int j = o + 1;
-      T av = T(0), ev = T(0);
-#pragma unroll
-      for (int y = 0; y < P; ++y) {
-        if (y < band_lo(j, K) || y > band_hi(j, K)) continue;
-        av = fma(a.M[o * P + y], zm[y], av);
-        ev = fma(a.Kst[o * P + y], zm[y], ev);
-        ev = fma(a.M[o * P + y], zk[y], ev);
-      }
-      AE[((0 * Q + oz) * Q + o) * P + x] = av;
-      AE[((1 * Q + oz) * Q + o) * P + x] = ev;
-    }
-  }
-  __syncthreads();
-
-  // ---- 3. x contraction, local residual, T^T along x  (lanes (oz, oy)) ----
-  if (lane < Q2) {
-    const int oz = lane / Q, oy = lane % Q;
-    T av[P], ev[P];
-#pragma unroll
-    for (int x = 0; x < P; ++x) {
-      av[x] = AE[((0 * Q + oz) * Q + oy) * P + x];
-      ev[x] = AE[((1 * Q + oz) * Q + oy) * P + x];
-    }
-    T r[Q], m[Q];
-#pragma unroll
-    for (int o = 0; o < Q; ++o) {
-      const int j = o + 1;
-      T s = T(0);
-#pragma unroll
-      for (int x = 0; x < P; ++x) {
-        if (x < band_lo(j, K) || x > band_hi(j, K)) continue;
-        s = fma(a.Kst[o * P + x], av[x], s);
-        s = fma(a.M[o * P + x], ev[x], s);
-      }
-      r[o] = B[oz * Q2 + oy * Q + o] - s;
-    }
-    fdm_forward<T, K>(a.f, r, m);
-#pragma unroll
-    for (int j = 0; j < Q; ++j) W0[(oz * Q + oy) * Q + j] = m[j];
-  }
-  __syncthreads();
-
-  // ---- 4. T^T along y  (lanes (oz, mx)) ----
-  if (lane < Q2) {
-    const int oz = lane / Q, mx = lane % Q;
-    T v[Q], m[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) v[i] = W0[(oz * Q + i) * Q + mx];
-    fdm_forward<T, K>(a.f, v, m);
-#pragma unroll
-    for (int j = 0; j < Q; ++j) W1[(oz * Q + j) * Q + mx] = m[j];
-  }
-  __syncthreads();
-
-  // ---- 5. T^T along z and 1/Lambda  (lanes (my, mx)) ----
-  if (lane < Q2) {
-    const int my = lane / Q, mx = lane % Q;
-    T v[Q], c[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) v[i] = W1[(i * Q + my) * Q + mx];
-    fdm_forward<T, K>(a.f, v, c);
-#pragma unroll
-    for (int j = 0; j < Q; ++j)
-      W0[(j * Q + my) * Q + mx] = c[j] * buf_load<T>(lr, (unsigned)(((j * Q + my) * Q + mx) * sizeof(T)), 0u);
-  }
-  __syncthreads();
-  // ---- 6. T along x  (lanes (mz, my)) ----
-  if (lane < Q2) {
-    const int mz = lane / Q, my = lane % Q;
-    T c[Q], d[Q];
-#pragma unroll
-    for (int j = 0; j < Q; ++j) c[j] = W0[(mz * Q + my) * Q + j];
-    fdm_backward<T, K>(a.f, c, d);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) W1[(mz * Q + my) * Q + i] = d[i];
-  }
-  __syncthreads();
-  // ---- 7. T along y  (lanes (mz, x)) ----
-  if (lane < Q2) {
-    const int mz = lane / Q, x = lane % Q;
-    T c[Q], d[Q];
-#pragma unroll
-    for (int j = 0; j < Q; ++j) c[j] = W1[(mz * Q + j) * Q + x];
-    fdm_backward<T, K>(a.f, c, d);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) W0[(mz * Q + i) * Q + x] = d[i];
-  }
-  __syncthreads();
-  // ---- 8. T along z, store the new interior plane by plane  (lanes (y, x)) ----
-  if (lane < Q2) {
-    T c[Q], d[Q];
-#pragma unroll
-    for (int j = 0; j < Q; ++j) c[j] = W0[j * Q2 + lane];
-    fdm_backward<T, K>(a.f, c, d);
-    const int y = 1 + lane / Q, x = 1 + lane % Q;
-    const unsigned off = (n1 * (unsigned)y + (unsigned)x) * (unsigned)sizeof(T);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) buf_store<T>(d[i], ur, off, sbase + splane * (i + 1));
   }
 }
 

@@ -54,6 +54,25 @@ struct TileLaunch {
   const double* G1;  // NO x NI (operator stiffness) or null
 };
 
+// Plane-streaming 3D kernels (constant coefficient): operator / residual and restriction.
+struct StreamLaunch {
+  const void* in;
+  const void* b;      // operator only: out = b - A u when non-null
+  void* out;
+  int n1_in, n1_out;
+  int ncell_out;      // cells per direction of the output grid; prolongation: of the coarse input grid
+  const double* G0;   // PO x W period rows (operator mass / restriction / prolongation)
+  const double* G1;   // PO x W operator stiffness period rows, or null
+  const double* Z0;   // ZO x (ZIN+1) z cell table (operator mass / restriction / prolongation)
+  const double* Z1;   // ZO x (ZIN+1) operator cell stiffness, or null
+};
+template <typename T, int K>
+hipError_t launch_stream_operator(const StreamLaunch& L, hipStream_t s);
+template <typename T, int K>
+hipError_t launch_stream_restrict(const StreamLaunch& L, hipStream_t s);
+template <typename T, int K>
+hipError_t launch_stream_prolong(const StreamLaunch& L, hipStream_t s);
+
 template <typename T, int K, int D>
 hipError_t launch_operator(const TileLaunch& L, hipStream_t s);
 template <typename T, int K, int D>

@@ -1,6 +1,7 @@
 // Launcher of the patch smoother kernel for one degree (VPS_PATCH_K), included
 // by patch_k<K>.hip so that the degrees compile in parallel.
 #include "kernels.h"
+#include "patch_wave.h"
 #include "launch.h"
 
 namespace vps {

@@ -1,0 +1,420 @@
+// Plane-streaming kernels for 3D constant-coefficient level operators: the
+// operator A u (and the residual b - A u) and the restriction P^T r.
+//
+// A workgroup owns an x-y tile of output cells and walks a chunk of cell
+// layers along z.  Per input plane it stages the plane's tile (with its x-y
+// halo) in LDS, contracts along x and then along y with the banded 1D
+// matrices (these are the same for every cell period of a uniform mesh, so a
+// work item handles one period of outputs with compile-time coefficients),
+// and folds the plane into the z direction in registers with the 1D matrices
+// of one z cell: an output plane is final once the last input plane of its
+// cell(s) has gone by, and the value on the vertex plane shared by two cells
+// is carried from one cell to the next.  Every input plane is read once per
+// chunk (plus one halo cell layer at the chunk's start and the x-y halo,
+// which neighbouring workgroups read at the same time from L2).
+//
+// Operator:     A = Kz (x) My (x) Mx + Mz (x) (My (x) Kx + Ky (x) Mx), the
+//               Kronecker-sum form of the Laplacian on Cartesian cells
+//               (Appendix A.3); per plane the x-y part yields mm = My Mx u and
+//               s = My Kx u + Ky Mx u, and the z part is Kz mm + Mz s.
+// Restriction:  P^T = Rz (x) Ry (x) Rx with R the transpose of the 1D
+//               prolongation (Section 2: the coarse space is embedded in the
+//               fine one); fine planes are folded into coarse planes by the
+//               1D restriction of one coarse cell.
+// Prolongation: u_fine += P e_coarse, P = Pz (x) Py (x) Px; the 2K fine
+//               planes of a coarse cell are interpolated from its K+1 coarse
+//               planes.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace vps {
+
+enum StreamKind { STREAM_OPERATOR = 0, STREAM_RESTRICT = 1, STREAM_PROLONG = 2 };
+
+// Shape of one kind and degree.  In x and y a period of PO outputs reads a
+// window of W inputs starting PI inputs after the previous period's.  TX, TY
+// periods per tile; ZIN input planes per z cell (the operator and the
+// prolongation share the vertex plane between neighbouring cells: K new
+// planes per cell; the restriction reads 2K fine planes per coarse cell);
+// ZO output planes accumulated per z cell.
+template <int KIND, int K>
+struct StreamShape {
+  static constexpr bool OP = KIND == STREAM_OPERATOR;
+  static constexpr bool PR = KIND == STREAM_PROLONG;
+  static constexpr int PO = PR ? 2 * K : K;
+  static constexpr int PI = (KIND == STREAM_RESTRICT) ? 2 * K : K;
+  static constexpr int W = OP ? 2 * K + 1 : PR ? K + 1 : 4 * K + 1;
+  static constexpr int TX = PR ? ((K == 1) ? 16 : (K == 2) ? 8 : (K == 3) ? 5 : 4)
+                               : ((K == 1) ? 32 : (K == 2) ? 16 : 8);
+  static constexpr int TY = PR ? ((K == 1) ? 32 : (K == 2) ? 16 : 8)
+                               : ((K == 1) ? 32 : (K == 2) ? 16 : (K == 3) ? 10 : 8);
+  static constexpr int NA = OP ? 2 : 1;  // arrays after the x contraction
+  static constexpr int ZIN = (KIND == STREAM_RESTRICT) ? 2 * K : K;
+  static constexpr int ZO = PR ? 2 * K : K + 1;
+  static constexpr int NOX = PO * TX, NOY = PO * TY;
+  static constexpr int NIX = PI * (TX - 1) + W, NIY = PI * (TY - 1) + W;
+  static constexpr int ITEMS = NOX * TY;  // y-pass work items (x output, y period)
+  static constexpr int NIT = (ITEMS + kBlock - 1) / kBlock;
+  static constexpr int NPF = (NIX * NIY + kBlock - 1) / kBlock;  // plane elements per thread
+  static constexpr int LDS_ELEMS = NIX * NIY + NA * NIY * NOX;
+  // nonzero band of period row j inside the window
+  static __host__ __device__ constexpr int lo(int j) { return (PR || j == 0) ? 0 : (OP ? K : 2 * K); }
+  static __host__ __device__ constexpr int hi(int j) { return OP ? 2 * K : PR ? K : 4 * K; }
+};
+
+template <typename T, int KIND, int K>
+struct StreamArgs {
+  using S = StreamShape<KIND, K>;
+  const T* __restrict__ in;
+  const T* __restrict__ b;  // operator only: out = b - A u if non-null
+  T* __restrict__ out;
+  int n1_in, n1_out;
+  int ncz;                  // cells of the output grid per direction
+  int tiles_x, tiles_y;     // x-y tiles
+  int cz;                   // z cells per chunk
+  unsigned nblocks;         // tiles_x * tiles_y * chunks
+  T G0[S::PO * S::W];       // operator: mass period rows; transfers: restriction / prolongation rows
+  T G1[S::OP ? S::PO * S::W : 1];  // operator: stiffness period rows
+  T Z0[S::ZO * (S::ZIN + 1)];      // [out][in]: operator: cell mass; transfers: cell block
+  T Z1[S::OP ? S::ZO * (S::ZIN + 1) : 1];  // operator: cell stiffness
+};
+
+template <typename T>
+__device__ inline T ld_or_zero(const T* __restrict__ p, size_t i, bool ok) {
+  return ok ? p[i] : T(0);
+}
+
+template <typename T, int KIND, int K>
+__global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIND, K> a) {
+  using S = StreamShape<KIND, K>;
+  constexpr bool OP = S::OP;
+  constexpr int PO = S::PO, PI = S::PI, W = S::W, TX = S::TX, TY = S::TY, NA = S::NA, ZIN = S::ZIN;
+  constexpr int NOX = S::NOX, NIX = S::NIX, NIY = S::NIY, NIT = S::NIT, NPF = S::NPF;
+  constexpr int ZW = ZIN + 1;  // row length of the z tables
+  __shared__ T U[NIY * NIX];
+  __shared__ T XA[NA * NIY * NOX];
+
+  // XCD-aware order: each of the 8 XCDs runs one contiguous range of blocks
+  const unsigned h = blockIdx.x;
+  const unsigned per = gridDim.x / kXcd;
+  const unsigned logical = (h % kXcd) * per + h / kXcd;
+  if (logical >= a.nblocks) return;
+  const int t = threadIdx.x;
+  const int tx = (int)(logical % (unsigned)a.tiles_x);
+  const unsigned rest = logical / (unsigned)a.tiles_x;
+  const int ty = (int)(rest % (unsigned)a.tiles_y);
+  const int chunk = (int)(rest / (unsigned)a.tiles_y);
+  const int cz0 = chunk * a.cz;
+  const int cz1 = min(a.ncz, cz0 + a.cz);
+  // first cell walked: one halo cell before the chunk (the prolongation needs none)
+  const int cs = S::PR ? cz0 : max(cz0 - 1, 0);
+
+  const int n1i = a.n1_in, n1o = a.n1_out;
+  const size_t pin = (size_t)n1i * n1i, pout = (size_t)n1o * n1o;
+  constexpr int HALO = S::PR ? 0 : PI;  // input nodes left of the tile's first output period
+  const int in0x = PI * TX * tx - HALO, in0y = PI * TY * ty - HALO;
+  const int out0x = PO * TX * tx, out0y = PO * TY * ty;
+
+  // this thread's elements of the input tile (plane offsets, in-grid flags)
+  unsigned pf_off[NPF];
+  bool pf_ok[NPF];
+#pragma unroll
+  for (int m = 0; m < NPF; ++m) {
+    const int e = t + kBlock * m;
+    const int x = e % NIX, y = e / NIX;
+    const int gx = in0x + x, gy = in0y + y;
+    pf_ok[m] = e < NIX * NIY && gx >= 0 && gx < n1i && gy >= 0 && gy < n1i;
+    pf_off[m] = pf_ok[m] ? (unsigned)(gy * n1i + gx) : 0u;
+  }
+  // this thread's output columns: items (xo, py), rows yo = py * PO + j
+  int it_xo[NIT], it_py[NIT];
+  bool it_ok[NIT];
+#pragma unroll
+  for (int m = 0; m < NIT; ++m) {
+    const int it = t + kBlock * m;
+    it_ok[m] = it < S::ITEMS;
+    it_xo[m] = it % NOX;
+    it_py[m] = it / NOX;
+  }
+
+  // prefetch registers: the next input plane's tile elements (and b of the next plane for the residual)
+  T pf[NPF];
+  T pb[NIT][PO];
+  auto prefetch = [&](int p) {
+    const T* src = a.in + (size_t)p * pin;
+#pragma unroll
+    for (int m = 0; m < NPF; ++m) pf[m] = ld_or_zero(src, pf_off[m], pf_ok[m]);
+    if constexpr (OP) {
+      if (a.b != nullptr) {
+        const T* bs = a.b + (size_t)p * pout;
+#pragma unroll
+        for (int m = 0; m < NIT; ++m)
+#pragma unroll
+          for (int j = 0; j < PO; ++j) {
+            const int gx = out0x + it_xo[m], gy = out0y + it_py[m] * PO + j;
+            const bool ok = it_ok[m] && gx < n1o && gy < n1o;
+            pb[m][j] = ld_or_zero(bs, ok ? (size_t)gy * n1o + gx : 0, ok);
+          }
+      }
+    }
+  };
+
+  // x-y contraction of the plane held in pf; the next plane's loads are issued first.
+  // Results: v0 (operator: mm = My Mx u; restriction: Ry Rx r), v1 (operator: s).
+  T v0[NIT][PO], v1[NIT][PO], cb[NIT][PO];
+  auto plane = [&](int p, int plast) {
+#pragma unroll
+    for (int m = 0; m < NPF; ++m)
+      if (t + kBlock * m < NIX * NIY) U[t + kBlock * m] = pf[m];
+    if constexpr (OP) {
+#pragma unroll
+      for (int m = 0; m < NIT; ++m)
+#pragma unroll
+        for (int j = 0; j < PO; ++j) cb[m][j] = pb[m][j];
+    }
+    if (p < plast) prefetch(p + 1);
+    __syncthreads();
+    // x: items (px, yi), outputs px * PO + j of row yi
+    for (int w = t; w < TX * NIY; w += kBlock) {
+      const int px = w % TX, yi = w / TX;
+      T u[W];
+#pragma unroll
+      for (int i = 0; i < W; ++i) u[i] = U[yi * NIX + px * PI + i];
+#pragma unroll
+      for (int j = 0; j < PO; ++j) {
+        T s0 = T(0), s1 = T(0);
+#pragma unroll
+        for (int i = S::lo(j); i <= S::hi(j); ++i) {
+          s0 = fma(a.G0[j * W + i], u[i], s0);
+          if constexpr (OP) s1 = fma(a.G1[j * W + i], u[i], s1);
+        }
+        XA[yi * NOX + px * PO + j] = s0;
+        if constexpr (OP) XA[NIY * NOX + yi * NOX + px * PO + j] = s1;
+      }
+    }
+    __syncthreads();
+    // y: items (xo, py), outputs rows py * PO + j
+#pragma unroll
+    for (int m = 0; m < NIT; ++m) {
+      if (!it_ok[m]) continue;
+      const int xo = it_xo[m], row0 = it_py[m] * PI;
+      T x0[W], x1[W];
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        x0[i] = XA[(row0 + i) * NOX + xo];
+        if constexpr (OP) x1[i] = XA[NIY * NOX + (row0 + i) * NOX + xo];
+      }
+#pragma unroll
+      for (int j = 0; j < PO; ++j) {
+        T s0 = T(0), s1 = T(0);
+#pragma unroll
+        for (int i = S::lo(j); i <= S::hi(j); ++i) {
+          s0 = fma(a.G0[j * W + i], x0[i], s0);
+          if constexpr (OP) {
+            s1 = fma(a.G0[j * W + i], x1[i], s1);
+            s1 = fma(a.G1[j * W + i], x0[i], s1);
+          }
+        }
+        v0[m][j] = s0;
+        if constexpr (OP) v1[m][j] = s1;
+      }
+    }
+  };
+
+  // write one output plane from acc[.][.][q]
+  T acc[NIT][PO][S::ZO];
+  auto emit = [&](int zp, int q) {
+    const bool zdir = zp == 0 || zp == n1o - 1;
+    T* dst = a.out + (size_t)zp * pout;
+#pragma unroll
+    for (int m = 0; m < NIT; ++m) {
+      if (!it_ok[m]) continue;
+      const int gx = out0x + it_xo[m];
+#pragma unroll
+      for (int j = 0; j < PO; ++j) {
+        const int gy = out0y + it_py[m] * PO + j;
+        if (gx >= n1o || gy >= n1o) continue;
+        const bool dir = zdir || gx == 0 || gx == n1o - 1 || gy == 0 || gy == n1o - 1;
+        dst[(size_t)gy * n1o + gx] = dir ? T(0) : acc[m][j][q];
+        // the last grid line of each direction lies outside every tile: written by its neighbour
+        if (gx == n1o - 2) dst[(size_t)gy * n1o + gx + 1] = T(0);
+        if (gy == n1o - 2) dst[(size_t)(gy + 1) * n1o + gx] = T(0);
+        if (gx == n1o - 2 && gy == n1o - 2) dst[(size_t)(gy + 1) * n1o + gx + 1] = T(0);
+      }
+    }
+  };
+  auto emit_zero_plane = [&](int zp) {
+    T* dst = a.out + (size_t)zp * pout;
+#pragma unroll
+    for (int m = 0; m < NIT; ++m) {
+      if (!it_ok[m]) continue;
+      const int gx = out0x + it_xo[m];
+#pragma unroll
+      for (int j = 0; j < PO; ++j) {
+        const int gy = out0y + it_py[m] * PO + j;
+        if (gx >= n1o || gy >= n1o) continue;
+        dst[(size_t)gy * n1o + gx] = T(0);
+        if (gx == n1o - 2) dst[(size_t)gy * n1o + gx + 1] = T(0);
+        if (gy == n1o - 2) dst[(size_t)(gy + 1) * n1o + gx] = T(0);
+        if (gx == n1o - 2 && gy == n1o - 2) dst[(size_t)(gy + 1) * n1o + gx + 1] = T(0);
+      }
+    }
+  };
+
+  const bool resid = OP && a.b != nullptr;
+  if constexpr (OP) {
+    // planes K*cs .. K*cz1; the vertex plane of each cell is folded into both of its cells
+    const int plast = K * cz1;
+    prefetch(K * cs);
+    plane(K * cs, plast);
+    T pm[NIT][PO], ps[NIT][PO];
+#pragma unroll
+    for (int m = 0; m < NIT; ++m)
+#pragma unroll
+      for (int j = 0; j < PO; ++j) {
+        pm[m][j] = v0[m][j];
+        ps[m][j] = v1[m][j];
+#pragma unroll
+        for (int i = 0; i <= K; ++i) acc[m][j][i] = T(0);
+      }
+    for (int c = cs; c < cz1; ++c) {
+      // start cell c: carry (acc[.][.][K] of cell c-1) plus its first plane
+#pragma unroll
+      for (int m = 0; m < NIT; ++m)
+#pragma unroll
+        for (int j = 0; j < PO; ++j) {
+          const T carry = acc[m][j][K];
+#pragma unroll
+          for (int i = 0; i <= K; ++i)
+            acc[m][j][i] = fma(a.Z1[i * ZW + 0], pm[m][j], a.Z0[i * ZW + 0] * ps[m][j]);
+          acc[m][j][0] += carry;
+          if (resid) acc[m][j][0] -= cb[m][j];
+        }
+#pragma unroll
+      for (int l = 1; l <= K; ++l) {
+        plane(K * c + l, plast);
+#pragma unroll
+        for (int m = 0; m < NIT; ++m)
+#pragma unroll
+          for (int j = 0; j < PO; ++j) {
+#pragma unroll
+            for (int i = 0; i <= K; ++i)
+              acc[m][j][i] = fma(a.Z1[i * ZW + l], v0[m][j], fma(a.Z0[i * ZW + l], v1[m][j], acc[m][j][i]));
+            if (resid && l < K) acc[m][j][l] -= cb[m][j];
+          }
+      }
+      // the vertex plane K*(c+1) also starts cell c+1
+#pragma unroll
+      for (int m = 0; m < NIT; ++m)
+#pragma unroll
+        for (int j = 0; j < PO; ++j) {
+          pm[m][j] = v0[m][j];
+          ps[m][j] = v1[m][j];
+        }
+      if (c >= cz0) {
+        if (resid) {
+#pragma unroll
+          for (int m = 0; m < NIT; ++m)
+#pragma unroll
+            for (int j = 0; j < PO; ++j)
+#pragma unroll
+              for (int i = 0; i < K; ++i) acc[m][j][i] = -acc[m][j][i];
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) emit(K * c + i, i);
+      }
+      // the b of plane K*(c+1) is subtracted when cell c+1 starts
+    }
+    if (cz1 == a.ncz) emit_zero_plane(K * a.ncz);
+  } else if constexpr (S::PR) {
+    // coarse planes K*cz0 .. K*cz1; fine planes 2K*c + j (j < 2K) from the K+1 planes of coarse cell c
+    const int plast = K * cz1;
+    prefetch(K * cs);
+    plane(K * cs, plast);
+    T pv[NIT][PO];
+#pragma unroll
+    for (int m = 0; m < NIT; ++m)
+#pragma unroll
+      for (int j = 0; j < PO; ++j) pv[m][j] = v0[m][j];
+    for (int c = cs; c < cz1; ++c) {
+#pragma unroll
+      for (int m = 0; m < NIT; ++m)
+#pragma unroll
+        for (int j = 0; j < PO; ++j)
+#pragma unroll
+          for (int q = 0; q < 2 * K; ++q) acc[m][j][q] = a.Z0[q * ZW + 0] * pv[m][j];
+#pragma unroll
+      for (int l = 1; l <= K; ++l) {
+        plane(K * c + l, plast);
+#pragma unroll
+        for (int m = 0; m < NIT; ++m)
+#pragma unroll
+          for (int j = 0; j < PO; ++j)
+#pragma unroll
+            for (int q = 0; q < 2 * K; ++q) acc[m][j][q] = fma(a.Z0[q * ZW + l], v0[m][j], acc[m][j][q]);
+      }
+#pragma unroll
+      for (int m = 0; m < NIT; ++m)
+#pragma unroll
+        for (int j = 0; j < PO; ++j) pv[m][j] = v0[m][j];
+      // add to the fine planes; Dirichlet nodes keep their (zero) value
+#pragma unroll
+      for (int q = 0; q < 2 * K; ++q) {
+        const int zf = 2 * K * c + q;
+        if (zf == 0) continue;
+        T* dst = a.out + (size_t)zf * pout;
+#pragma unroll
+        for (int m = 0; m < NIT; ++m) {
+          if (!it_ok[m]) continue;
+          const int gx = out0x + it_xo[m];
+          if (gx == 0 || gx >= n1o - 1) continue;
+#pragma unroll
+          for (int j = 0; j < PO; ++j) {
+            const int gy = out0y + it_py[m] * PO + j;
+            if (gy == 0 || gy >= n1o - 1) continue;
+            dst[(size_t)gy * n1o + gx] += acc[m][j][q];
+          }
+        }
+      }
+    }
+  } else {
+    // fine planes 2K*cs .. 2K*cz1 - 1, each inside one coarse cell
+    const int plast = 2 * K * cz1 - 1;
+    prefetch(2 * K * cs);
+#pragma unroll
+    for (int m = 0; m < NIT; ++m)
+#pragma unroll
+      for (int j = 0; j < PO; ++j)
+#pragma unroll
+        for (int i = 0; i <= K; ++i) acc[m][j][i] = T(0);
+    for (int c = cs; c < cz1; ++c) {
+#pragma unroll
+      for (int l = 0; l < 2 * K; ++l) {
+        plane(2 * K * c + l, plast);
+#pragma unroll
+        for (int m = 0; m < NIT; ++m)
+#pragma unroll
+          for (int j = 0; j < PO; ++j) {
+            if (l == 0) {
+              const T carry = acc[m][j][K];
+#pragma unroll
+              for (int i = 0; i <= K; ++i) acc[m][j][i] = a.Z0[i * ZW + 0] * v0[m][j];
+              acc[m][j][0] += carry;
+            } else {
+#pragma unroll
+              for (int i = 0; i <= K; ++i) acc[m][j][i] = fma(a.Z0[i * ZW + l], v0[m][j], acc[m][j][i]);
+            }
+          }
+      }
+      if (c >= cz0) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) emit(K * c + i, i);
+      }
+    }
+    if (cz1 == a.ncz) emit_zero_plane(K * a.ncz);
+  }
+}
+
+}  // namespace vps

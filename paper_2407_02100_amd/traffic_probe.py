@@ -30,7 +30,7 @@ COPY_BYTES = 512 * 1024 * 1024  # bytes read by the calibration copy (and writte
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.h", "patch_impl.h"):
+    for f in ("patch_wave.h", "patch_impl.h"):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
