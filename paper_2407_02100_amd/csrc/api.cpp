@@ -33,9 +33,8 @@ struct Level {
   Mat Mfull, Kfull, Mh[2], Kh[2];
   Mat T1;                   // FDM eigenvectors (q x q)
   std::vector<double> lam;  // FDM eigenvalues (q)
+  std::vector<double> lam_int;  // the same in the even/odd mode order (3D)
   Mat Te, To;               // even/odd blocks of T1 (symmetric / antisymmetric modes)
-  std::vector<double> ilam; // 1 / (lam_a + lam_b [+ lam_c]) in the even/odd mode order
-  void* ilam_dev[2] = {nullptr, nullptr};  // [0] FP64, [1] FP32
   Mat opM, opK;             // operator tile blocks
   Mat restrictG;            // transfer tile: this level -> level-1
   Mat prolongG;             // transfer tile: level-1 -> this level
@@ -257,11 +256,8 @@ void build_level(Level& L, int k, int d, int ncell) {
   if (!vps::fdm_even_odd(q, L.T1, &L.Te, &L.To, &order)) {
     L.Te.clear();  // no even/odd structure: the one-patch-per-wave kernel is not used
   } else if (d == 3) {
-    L.ilam.assign((size_t)q * q * q, 0.0);
-    for (int jz = 0; jz < q; ++jz)
-      for (int jy = 0; jy < q; ++jy)
-        for (int jx = 0; jx < q; ++jx)
-          L.ilam[((size_t)jz * q + jy) * q + jx] = 1.0 / (L.lam[order[jx]] + L.lam[order[jy]] + L.lam[order[jz]]);
+    L.lam_int.resize(q);
+    for (int j = 0; j < q; ++j) L.lam_int[j] = L.lam[order[j]];
   }
   // operator tile
   {
@@ -386,8 +382,8 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   P.lam = L.lam.data();
   P.Te = L.Te.empty() ? nullptr : L.Te.data();
   P.To = L.Te.empty() ? nullptr : L.To.data();
-  P.ilam = L.ilam_dev[t == VPS_F64 ? 0 : 1];
-  if (!P.ilam || !P.Te) P.pb = P.pb > 0 ? P.pb : -1;  // -1: generic kernel, automatic batch
+  P.lam_int = L.lam_int.empty() ? nullptr : L.lam_int.data();
+  if (!P.lam_int || !P.Te) P.pb = P.pb > 0 ? P.pb : -1;  // -1: generic kernel, automatic batch
   return dispatch_tkd(t, k, d, [&]<typename T, int K, int D>() { return vps::launch_patch_color<T, K, D>(P, c->stream); });
 }
 
@@ -560,6 +556,25 @@ vps_status dots(vps_context* c, const double* x, const double* y, const double* 
   return VPS_OK;
 }
 
+// One FP32 V-cycle on the finest level: F.b holds the residual in FP32, the
+// correction is left in F.u (FP32).
+hipError_t vcycle_f32_resident(vps_context* c) {
+  const int L = (int)c->lv.size() - 1;
+  if (c->timer.on) c->timer.tot.vcycles += 1;
+  return vcycle_level(c, L, c->lv[L].b, c->lv[L].u);
+}
+
+vps_status dots_z32(vps_context* c, const double* r, const float* z, const double* q, size_t n, double* out) {
+  int nblk = 0;
+  VPS_HIP(c, vps::launch_dot_z32(r, z, q, n, c->partial, &nblk, c->stream));
+  const int nd = q ? 2 : 1;
+  VPS_HIP(c, vps::launch_dot_final(c->partial, nblk, nd, c->dscal, c->stream));
+  VPS_HIP(c, hipMemcpyAsync(c->hscal, c->dscal, nd * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  VPS_HIP(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < nd; ++i) out[i] = c->hscal[i];
+  return VPS_OK;
+}
+
 vps_status ensure_cg(vps_context* c) {
   if (c->cg_r) return VPS_OK;
   const size_t n = c->lv.back().nodes * sizeof(double);
@@ -578,8 +593,6 @@ void free_all(vps_context* c) {
     hipFree(L.rho64);
     hipFree(L.rho32);
     hipFree(L.scal);
-    hipFree(L.ilam_dev[0]);
-    hipFree(L.ilam_dev[1]);
   }
   for (int i = 0; i < 2; ++i) {
     hipFree(c->cT0[i]);
@@ -653,10 +666,6 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
     return e != hipSuccess;
   };
   for (Level& L : c->lv) {
-    if (!L.ilam.empty() && C.coef == VPS_COEF_CONST) {
-      if (chk(upload<double>(L.ilam, &L.ilam_dev[0], c->stream), "upload")) return bail(VPS_E_HIP);
-      if (chk(upload<float>(L.ilam, &L.ilam_dev[1], c->stream), "upload")) return bail(VPS_E_HIP);
-    }
     if (chk(hipMalloc(&L.u, L.nodes * esize(t)), "hipMalloc")) return bail(VPS_E_NOMEM);
     if (chk(hipMalloc(&L.b, L.nodes * esize(t)), "hipMalloc")) return bail(VPS_E_NOMEM);
     if (chk(hipMalloc(&L.r, L.nodes * esize(t)), "hipMalloc")) return bail(VPS_E_NOMEM);
@@ -908,6 +917,12 @@ vps_status vps_vcycle(vps_context* c, const double* r, double* z) {
   return VPS_OK;
 }
 
+// Preconditioned CG in FP64 (Section 4).  With an FP32 V-cycle the
+// preconditioner is not exactly symmetric, so the flexible form is used:
+// beta = (z_new, r_new - r_old) / (z_old, r_old) with r_new - r_old = -alpha q.
+// FP32 V-cycle: the CG update writes the FP32 residual the V-cycle reads, and
+// the FP32 correction is consumed directly by the dot products and the update
+// of the search direction (no FP64 copy of it).
 vps_status vps_solve(vps_context* c, const double* b, double* x, double rtol, int maxit, vps_solve_info* info) {
   if (!c || !b || !x) return fail(c, VPS_E_ARG, "null argument");
   if (!(rtol > 0.0) || maxit < 0) return fail(c, VPS_E_ARG, "rtol must be > 0 and maxit >= 0");
@@ -916,29 +931,44 @@ vps_status vps_solve(vps_context* c, const double* b, double* x, double rtol, in
   if (vps_status s = ensure_cg(c)) return s;
   const int L = (int)c->lv.size() - 1;
   const size_t n = c->lv[L].nodes;
-  const bool flexible = vdt(c) == VPS_F32;
+  const bool mixed = vdt(c) == VPS_F32;
   double *r = c->cg_r, *p = c->cg_p, *q = c->cg_q, *z = c->cg_z;
+  float* r32 = mixed ? (float*)c->lv[L].b : nullptr;
+  const float* z32 = mixed ? (const float*)c->lv[L].u : nullptr;
   vps_solve_info inf{};
   for (long long f : c->fallback) inf.fallback_patches += f;
   VPS_HIP(c, hipEventRecord(c->ev0, c->stream));
-  VPS_HIP(c, vps::launch_fill<double>(x, 0.0, n, c->stream));
-  VPS_HIP(c, hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   double s2[2];
   if (vps_status st = dots(c, b, b, nullptr, nullptr, n, s2)) return st;
   const double bn = std::sqrt(s2[0]);
   if (!std::isfinite(bn)) return fail(c, VPS_E_NONFINITE, "right-hand side is not finite");
   vps_status result = VPS_E_NOT_CONVERGED;
+  bool x_set = false;  // x is written by the first update (x_0 = 0)
   if (bn == 0.0) {
     result = VPS_OK;
-  } else {
-    VPS_HIP(c, do_vcycle(c, r, z));
-    if (vps_status st = dots(c, r, z, nullptr, nullptr, n, s2)) return st;
-    double rz = s2[0];
-    VPS_HIP(c, hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  } else if (maxit > 0) {
+    // z_0 = M b, p_0 = z_0
+    double rz;
+    int ti;
+    if (mixed) {
+      ti = tbegin(c, PH_CG_VEC, L);
+      VPS_HIP(c, (vps::launch_cast<double, float>(b, r32, n, c->stream)));
+      tend(c, ti);
+      VPS_HIP(c, vcycle_f32_resident(c));
+      ti = tbegin(c, PH_CG_VEC, L);
+      if (vps_status st = dots_z32(c, b, z32, nullptr, n, s2)) return st;
+      VPS_HIP(c, (vps::launch_cast<float, double>(z32, p, n, c->stream)));
+      tend(c, ti);
+    } else {
+      VPS_HIP(c, do_vcycle(c, b, z));
+      if (vps_status st = dots(c, b, z, nullptr, nullptr, n, s2)) return st;
+      std::swap(p, z);  // p_0 = z_0 without a copy; z is overwritten by the next V-cycle
+    }
+    rz = s2[0];
     int it = 0;
     while (it < maxit) {
       ++it;
-      int ti = tbegin(c, PH_CG_OP, L);
+      ti = tbegin(c, PH_CG_OP, L);
       VPS_HIP(c, do_operator(c, L, p, nullptr, q, VPS_F64));
       tend(c, ti);
       ti = tbegin(c, PH_CG_VEC, L);
@@ -951,7 +981,9 @@ vps_status vps_solve(vps_context* c, const double* b, double* x, double rtol, in
         break;
       }
       int nblk = 0;
-      VPS_HIP(c, vps::launch_cg_update(alpha, p, q, x, r, n, c->partial, &nblk, c->stream));
+      VPS_HIP(c, vps::launch_cg_update(alpha, p, q, x, x_set ? r : b, r, r32, !x_set, n, c->partial, &nblk,
+                                       c->stream));
+      x_set = true;
       VPS_HIP(c, vps::launch_dot_final(c->partial, nblk, 1, c->dscal, c->stream));
       VPS_HIP(c, hipMemcpyAsync(c->hscal, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
       VPS_HIP(c, hipStreamSynchronize(c->stream));
@@ -973,30 +1005,32 @@ vps_status vps_solve(vps_context* c, const double* b, double* x, double rtol, in
           break;
         }
         restarted = true;
+        if (mixed) VPS_HIP(c, (vps::launch_cast<double, float>(r, r32, n, c->stream)));
       }
-      VPS_HIP(c, do_vcycle(c, r, z));
-      ti = tbegin(c, PH_CG_VEC, L);
-      double rzn, zq;
-      if (flexible && !restarted) {
-        if (vps_status st = dots(c, r, z, z, q, n, s2)) return st;
-        rzn = s2[0];
-        zq = s2[1];
+      double rzn, zq = 0.0;
+      if (mixed) {
+        VPS_HIP(c, vcycle_f32_resident(c));
+        ti = tbegin(c, PH_CG_VEC, L);
+        if (vps_status st = dots_z32(c, r, z32, restarted ? nullptr : q, n, s2)) return st;
       } else {
+        VPS_HIP(c, do_vcycle(c, r, z));
+        ti = tbegin(c, PH_CG_VEC, L);
         if (vps_status st = dots(c, r, z, nullptr, nullptr, n, s2)) return st;
-        rzn = s2[0];
-        zq = 0.0;
       }
-      // flexible: beta = (z_new, r_new - r_old) / (z_old, r_old) with r_new - r_old = -alpha q
-      const double beta = (flexible && !restarted) ? (-alpha * zq) / rz : rzn / rz;
+      rzn = s2[0];
+      if (mixed && !restarted) zq = s2[1];
+      const double beta = (mixed && !restarted) ? (-alpha * zq) / rz : rzn / rz;
       rz = rzn;
       if (!std::isfinite(beta)) {
         result = fail(c, VPS_E_NONFINITE, "CG breakdown: beta is not finite");
         break;
       }
-      VPS_HIP(c, vps::launch_xpay(z, beta, p, n, c->stream));
+      if (mixed) VPS_HIP(c, vps::launch_xpay_z32(z32, beta, p, n, c->stream));
+      else VPS_HIP(c, vps::launch_xpay(z, beta, p, n, c->stream));
       tend(c, ti);
     }
   }
+  if (!x_set) VPS_HIP(c, vps::launch_fill<double>(x, 0.0, n, c->stream));
   // final true residual
   VPS_HIP(c, do_operator(c, L, x, b, q, VPS_F64));
   if (vps_status st = dots(c, q, q, nullptr, nullptr, n, s2)) return st;

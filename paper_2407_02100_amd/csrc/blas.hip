@@ -50,20 +50,50 @@ __device__ inline double block_sum(double v, double* red) {
   return out;
 }
 
+// x += alpha p (x = alpha p when x_zero), r = r_in - alpha q, optionally r32 = (float) r,
+// partial sums of r.r
 __global__ void __launch_bounds__(kBlock) cg_update_kernel(double alpha, const double* __restrict__ p,
                                                            const double* __restrict__ q, double* __restrict__ x,
-                                                           double* __restrict__ r, size_t n,
-                                                           double* __restrict__ partial) {
+                                                           const double* r_in, double* r, float* __restrict__ r32,
+                                                           bool x_zero, size_t n, double* __restrict__ partial) {
   __shared__ double red[kBlock];
   double acc = 0.0;
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
+    x[i] = x_zero ? alpha * p[i] : x[i] + alpha * p[i];
+    const double ri = r_in[i] - alpha * q[i];
     r[i] = ri;
+    if (r32) r32[i] = (float)ri;
     acc += ri * ri;
   }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// partial sums of (r.z) and, if q is given, (z.q), with z in FP32
+__global__ void __launch_bounds__(kBlock) dot_z32_kernel(const double* __restrict__ r, const float* __restrict__ z,
+                                                         const double* __restrict__ q, size_t n,
+                                                         double* __restrict__ partial) {
+  __shared__ double red[kBlock];
+  double a1 = 0.0, a2 = 0.0;
+  const bool two = q != nullptr;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    const double zi = (double)z[i];
+    a1 += r[i] * zi;
+    if (two) a2 += zi * q[i];
+  }
+  const double s1 = block_sum(a1, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s1;
+  if (two) {
+    const double s2 = block_sum(a2, red);
+    if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+// p = (double) z + beta p
+__global__ void __launch_bounds__(kBlock) xpay_z32_kernel(const float* __restrict__ z, double beta,
+                                                          double* __restrict__ p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    p[i] = (double)z[i] + beta * p[i];
 }
 
 __global__ void __launch_bounds__(kBlock) dot_partial_kernel(const double* __restrict__ x,
@@ -248,11 +278,25 @@ static int dot_blocks(size_t n) {
   return (int)g;
 }
 
-hipError_t launch_cg_update(double alpha, const double* p, const double* q, double* x, double* r, size_t n,
-                            double* partial, int* nblk, hipStream_t s) {
+hipError_t launch_cg_update(double alpha, const double* p, const double* q, double* x, const double* r_in,
+                            double* r, float* r32, bool x_zero, size_t n, double* partial, int* nblk,
+                            hipStream_t s) {
   const int g = dot_blocks(n);
   *nblk = g;
-  cg_update_kernel<<<g, kBlock, 0, s>>>(alpha, p, q, x, r, n, partial);
+  cg_update_kernel<<<g, kBlock, 0, s>>>(alpha, p, q, x, r_in, r, r32, x_zero, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_z32(const double* r, const float* z, const double* q, size_t n, double* partial, int* nblk,
+                          hipStream_t s) {
+  const int g = dot_blocks(n);
+  *nblk = g;
+  dot_z32_kernel<<<g, kBlock, 0, s>>>(r, z, q, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpay_z32(const float* z, double beta, double* p, size_t n, hipStream_t s) {
+  xpay_z32_kernel<<<grid_for(n), kBlock, 0, s>>>(z, beta, p, n);
   return hipGetLastError();
 }
 

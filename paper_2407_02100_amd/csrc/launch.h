@@ -38,7 +38,7 @@ struct PatchLaunch {
   // reciprocal eigenvalue sums in the internal mode order (device, dtype of u)
   const double* Te;    // K x K
   const double* To;    // (K-1) x (K-1)
-  const void* ilam;    // Q^3
+  const double* lam_int;  // Q eigenvalues in the even/odd mode order (host), or null
 };
 
 template <typename T, int K, int D>
@@ -117,9 +117,16 @@ hipError_t launch_cast(const void* in, void* out, size_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_axpy(double a, const void* x, void* y, size_t n, hipStream_t s);  // y += a x
 hipError_t launch_xpay(const double* x, double a, double* y, size_t n, hipStream_t s);  // y = x + a y
-// x += alpha p; r -= alpha q; partial sums of r.r into partial[0..nblk)
-hipError_t launch_cg_update(double alpha, const double* p, const double* q, double* x, double* r, size_t n,
-                            double* partial, int* nblk, hipStream_t s);
+// x += alpha p (x = alpha p if x_zero); r = r_in - alpha q (r_in may be r); r32 = (float) r if r32 is
+// non-null; partial sums of r.r into partial[0..nblk)
+hipError_t launch_cg_update(double alpha, const double* p, const double* q, double* x, const double* r_in,
+                            double* r, float* r32, bool x_zero, size_t n, double* partial, int* nblk,
+                            hipStream_t s);
+// partial sums of (r.z) into partial[0..nblk) and, if q is non-null, (z.q) into partial[nblk..2 nblk); z FP32
+hipError_t launch_dot_z32(const double* r, const float* z, const double* q, size_t n, double* partial, int* nblk,
+                          hipStream_t s);
+// p = z + beta p with z FP32
+hipError_t launch_xpay_z32(const float* z, double beta, double* p, size_t n, hipStream_t s);
 // partial sums of (x.y) into partial[0..nblk) and, if x2/y2 are given, (x2.y2) into partial[nblk..2 nblk)
 hipError_t launch_dot_partial(const double* x, const double* y, const double* x2, const double* y2, size_t n,
                               double* partial, int* nblk, hipStream_t s);

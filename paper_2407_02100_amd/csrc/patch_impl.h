@@ -66,7 +66,6 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
       WaveArgs<T, K> w;
       w.u = a.u;
       w.b = a.b;
-      w.ilam = (const T*)L.ilam;
       w.n1 = a.n1;
       for (int e = 0; e < 3; ++e) {
         w.v0[e] = a.v0[e];
@@ -88,8 +87,7 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
       }
       for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
       for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
-      // one wave per patch, WAVES patches per workgroup; the grid is padded to a
-      // multiple of the XCD count
+      for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];
       // one wave per patch; the grid is padded to a multiple of the XCD count
       const unsigned grid = (w.npatch + kXcd - 1) / kXcd * kXcd;
       patch_wave3_kernel<T, K><<<grid, 64, 0, s>>>(w);

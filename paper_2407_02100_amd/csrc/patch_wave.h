@@ -22,17 +22,20 @@ namespace vps {
 // under reversal of the node order, so each eigenvector is symmetric (K of
 // them) or antisymmetric (K-1).  T^T v then needs the folded sums/differences
 // of v and the K x K and (K-1) x (K-1) blocks Te, To only; the modes are kept
-// in the internal order [symmetric..., antisymmetric...] throughout, and the
-// reciprocal eigenvalue sums 1/(lam_x + lam_y + lam_z) come from a per-level
-// table in that order.
+// in the internal order [symmetric..., antisymmetric...] throughout, and each
+// lane forms its reciprocal eigenvalue sums 1/(lam_x + lam_y + lam_z) from
+// the 1D eigenvalues in that order (kernel arguments): a table in memory
+// would cost vector-memory instructions, the unit this kernel is bound by.
 //
-// Lanes of one wave64 per patch:
-//   1. z contraction of the closure columns (y, x): boundary columns carry
-//      2K+1 values, interior columns only their two end values;
-//   2. y contraction of the (z-out, x) lines;
-//   3. x contraction of the (z-out, y-out) lines, local residual, T^T along x;
-//   4. T^T along y;  5. T^T along z, 1/Lambda, T along z;  6. T along y;
-//   7. T along x and store.
+// Stages of the wave64 that owns a patch:
+//   0. every global load of the patch, issued before any arithmetic so that
+//      they are in flight together: the closure columns (y, x) along z
+//      (boundary columns carry 2K+1 values, interior columns only their two
+//      end values) and the right-hand side columns of the interior;
+//   1. z contraction of the closure columns;  2. y contraction of the
+//      (z-out, x) lines;  3. x contraction of the (z-out, y-out) lines, local
+//      residual, T^T along x;  4. T^T along y;  5. T^T along z and 1/Lambda;
+//   6. T along x;  7. T along y;  8. T along z and store, plane by plane.
 // One wave64 (one workgroup) per patch.  Workgroups are mapped so that each
 // of the 8 XCDs owns one contiguous slab of the color's patches
 // (lexicographic order), which keeps the closure planes that neighbouring
@@ -100,7 +103,6 @@ template <typename T, int K>
 struct WaveArgs {
   T* __restrict__ u;
   const T* __restrict__ b;
-  const T* __restrict__ ilam;  // Q^3 reciprocal eigenvalue sums, internal mode order, [mz][my][mx]
   int n1;
   int v0[3];
   int np[3];
@@ -112,6 +114,7 @@ struct WaveArgs {
   T M[(2 * K - 1) * (2 * K + 1)];    // interior rows of the 2-cell patch mass matrix
   T Kst[(2 * K - 1) * (2 * K + 1)];  // ... and stiffness matrix
   WaveFdm<T, K> f;
+  T lam[2 * K - 1];  // 1D generalized eigenvalues in the internal mode order
 };
 
 template <int K>
@@ -180,18 +183,29 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
                       n2 * (size_t)(K * (a.v0[2] + 2 * pz - 1));
   const __amdgpu_buffer_rsrc_t ur = make_rsrc(a.u, a.vec_bytes);
   const __amdgpu_buffer_rsrc_t br = make_rsrc(a.b, a.vec_bytes);
-  const __amdgpu_buffer_rsrc_t lr = make_rsrc(a.ilam, (unsigned)(Q * Q2 * sizeof(T)));
   const unsigned sbase = (unsigned)(base * sizeof(T));  // patch origin, bytes
   const unsigned splane = (unsigned)(n2 * sizeof(T));   // one z plane, bytes
 
+  // ---- 0. every global load of the patch, issued before any arithmetic ----
+  int by = 0, bx = 0;
+  boundary_column<K>(lane < NB ? lane : 0, by, bx);
+  T vb[P];
+  if (lane < NB) {
+    const unsigned off = (n1 * (unsigned)by + (unsigned)bx) * (unsigned)sizeof(T);
+#pragma unroll
+    for (int z = 0; z < P; ++z) vb[z] = buf_load<T>(ur, off, sbase + splane * z);
+  }
+  const int iy = 1 + lane / Q, ix = 1 + lane % Q;
+  T v0 = T(0), v1 = T(0), bv[Q];
+  if (lane < Q2) {
+    const unsigned off = (n1 * (unsigned)iy + (unsigned)ix) * (unsigned)sizeof(T);
+    v0 = buf_load<T>(ur, off, sbase);
+    v1 = buf_load<T>(ur, off, sbase + splane * (P - 1));
+#pragma unroll
+    for (int o = 0; o < Q; ++o) bv[o] = buf_load<T>(br, off, sbase + splane * (o + 1));
+  }
   // ---- 1. z contraction; right-hand side columns into LDS ----
   if (lane < NB) {
-    int y, x;
-    boundary_column<K>(lane, y, x);
-    const unsigned off = (n1 * (unsigned)y + (unsigned)x) * (unsigned)sizeof(T);
-    T v[P];
-#pragma unroll
-    for (int z = 0; z < P; ++z) v[z] = buf_load<T>(ur, off, sbase + splane * z);
 #pragma unroll
     for (int o = 0; o < Q; ++o) {
       const int j = o + 1;
@@ -199,27 +213,24 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
 #pragma unroll
       for (int z = 0; z < P; ++z) {
         if (z < band_lo(j, K) || z > band_hi(j, K)) continue;
-        zm = fma(a.M[o * P + z], v[z], zm);
-        zk = fma(a.Kst[o * P + z], v[z], zk);
+        zm = fma(a.M[o * P + z], vb[z], zm);
+        zk = fma(a.Kst[o * P + z], vb[z], zk);
       }
-      Z[(0 * Q + o) * P2 + y * P + x] = zm;
-      Z[(1 * Q + o) * P2 + y * P + x] = zk;
+      Z[(0 * Q + o) * P2 + by * P + bx] = zm;
+      Z[(1 * Q + o) * P2 + by * P + bx] = zk;
     }
   }
   if (lane < Q2) {
-    const int y = 1 + lane / Q, x = 1 + lane % Q;
-    const unsigned off = (n1 * (unsigned)y + (unsigned)x) * (unsigned)sizeof(T);
-    const T v0 = buf_load<T>(ur, off, sbase), v1 = buf_load<T>(ur, off, sbase + splane * (P - 1));
 #pragma unroll
-    for (int o = 0; o < Q; ++o) B[o * Q2 + lane] = buf_load<T>(br, off, sbase + splane * (o + 1));
+    for (int o = 0; o < Q; ++o) B[o * Q2 + lane] = bv[o];
 #pragma unroll
     for (int o = 0; o < Q; ++o) {
       const int j = o + 1;
       T zm = T(0), zk = T(0);
       if (band_lo(j, K) == 0) { zm = fma(a.M[o * P], v0, zm); zk = fma(a.Kst[o * P], v0, zk); }
       if (band_hi(j, K) == P - 1) { zm = fma(a.M[o * P + P - 1], v1, zm); zk = fma(a.Kst[o * P + P - 1], v1, zk); }
-      Z[(0 * Q + o) * P2 + y * P + x] = zm;
-      Z[(1 * Q + o) * P2 + y * P + x] = zk;
+      Z[(0 * Q + o) * P2 + iy * P + ix] = zm;
+      Z[(1 * Q + o) * P2 + iy * P + ix] = zk;
     }
   }
   __syncthreads();
@@ -299,7 +310,20 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
     fdm_forward<T, K>(a.f, v, c);
 #pragma unroll
     for (int j = 0; j < Q; ++j)
-      W0[(j * Q + my) * Q + mx] = c[j] * buf_load<T>(lr, (unsigned)(((j * Q + my) * Q + mx) * sizeof(T)), 0u);
+      {
+        T lmy = a.lam[0], lmx = a.lam[0];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          lmy = (my == i) ? a.lam[i] : lmy;
+          lmx = (mx == i) ? a.lam[i] : lmx;
+        }
+        const T s2 = lmy + lmx;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          if constexpr (sizeof(T) == 4) W0[(j * Q + my) * Q + mx] = c[j] * __builtin_amdgcn_rcpf(s2 + a.lam[j]);
+          else W0[(j * Q + my) * Q + mx] = c[j] / (s2 + a.lam[j]);
+        }
+      }
   }
   __syncthreads();
   // ---- 6. T along x  (lanes (mz, my)) ----
