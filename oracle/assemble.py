@@ -141,6 +141,25 @@ def matvec_kron(dim: int, k: int, n_cells: int, u: np.ndarray) -> np.ndarray:
     return out
 
 
+def matvec_cells(dim: int, k: int, n_cells: int, rho: np.ndarray | None, u: np.ndarray) -> np.ndarray:
+    """A(rho) u without storing A: the cell-by-cell sum of ``assemble`` applied to u.
+
+    Each cell contributes rho_c E (u restricted to its nodes) to its nodes
+    (the same element matrix and node numbering as ``assemble``); the
+    Dirichlet entries of the result are set to 0 and those of u must be 0.
+    """
+    h = 1.0 / n_cells
+    E = element_matrix(dim, k, h)
+    idx = cell_node_indices(dim, k, n_cells)
+    w = np.ones(idx.shape[0]) if rho is None else np.asarray(rho, dtype=np.float64).reshape(-1)
+    u = np.asarray(u, dtype=np.float64)
+    contrib = (u[idx] @ E.T) * w[:, None]
+    n = n1d(k, n_cells) ** dim
+    out = np.bincount(idx.reshape(-1), weights=contrib.reshape(-1), minlength=n)
+    out[~free_mask_flat(dim, k, n_cells)] = 0.0
+    return out
+
+
 def all_cells(dim: int, n_cells: int):
     for rev in itertools.product(range(n_cells), repeat=dim):
         yield tuple(reversed(rev))

@@ -96,3 +96,14 @@ def test_dirichlet_rows_zero_and_symmetric():
     assert np.allclose(Ad, Ad.T, atol=1e-15)
     ev = np.linalg.eigvalsh(Ad[np.ix_(free, free)])
     assert ev.min() > 0
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 6), (2, 3, 5), (3, 1, 5), (3, 2, 4), (3, 4, 3)])
+def test_matvec_cells_equals_assembled(dim, k, N):
+    """The unassembled variable-coefficient product equals the assembled CSR matrix times u."""
+    rng = np.random.default_rng(dim * 100 + k * 10 + N)
+    rho = np.exp(rng.standard_normal(N ** dim))
+    u = rng.standard_normal((k * N + 1) ** dim)
+    u[~mesh.free_mask_flat(dim, k, N)] = 0.0
+    A = assemble.assemble(dim, k, N, rho)
+    assert np.allclose(assemble.matvec_cells(dim, k, N, rho, u), A @ u, rtol=0, atol=1e-12 * abs(A @ u).max())
