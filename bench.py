@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "patch_sweep_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_02100_amd", "csrc", f) for f in ("patch_wave.h", "patch_impl.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_02100_amd", "csrc", f) for f in ("patch_wave.h",)]
 
 
 def kernel_source_hash() -> str:
@@ -67,6 +67,13 @@ def color_counts(dim: int, k: int, n: int):
 def sweep_bytes(dim: int, k: int, n: int, word: int) -> int:
     """Algorithmic bytes of one sweep: per color read the closures of u, read b and write u on the interiors."""
     return sum((clo + 2 * inner) * word for clo, inner in color_counts(dim, k, n))
+
+
+def sweep_bytes_separated(dim: int, k: int, n: int, word: int) -> int:
+    """Algorithm 3: per color the global residual (read u and b, write r on all nodes), then the
+    local solves (read r and u, write u on the interiors)."""
+    nodes = (k * n + 1) ** dim
+    return sum((3 * nodes + 3 * inner) * word for _, inner in color_counts(dim, k, n))
 
 
 # ---------------------------------------------------------------------------
@@ -134,8 +141,53 @@ def _solve(torch, vps, vi, name, vcycle=None, reps=3):
             "rel_residual_true": max(i["rel_residual_true"] for i in infos)}, x
 
 
+def _median_ms(torch, fn, reps=5, inner=20):
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(inner):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / inner)
+    return sorted(times)[len(times) // 2]
+
+
+def run_sweep_protocol(torch, vps, vi, name="poisson3d_q4_n128"):
+    """Finest-level sweeps alone: 3 warm-ups, median of 5 runs of 20 sweeps, both algorithms; t_apply."""
+    w = vi.WORKLOADS[name]
+    dim, k, N = w["dim"], w["degree"], w["n_cells"]
+    tdt = torch.float32 if w["vcycle"] == "f32" else torch.float64
+    word = 4 if w["vcycle"] == "f32" else 8
+    b = torch.from_numpy(vi.seeded_vector(dim, k, N, w["rhs_seed"])).to("cuda", tdt)
+    u = torch.from_numpy(vi.seeded_vector(dim, k, N, 100 + w["rhs_seed"])).to("cuda", tdt)
+    n = u.numel()
+    out = {"workload": name, "dtype": w["vcycle"]}
+    for alg, nbytes in (("combined", sweep_bytes(dim, k, N, word)),
+                        ("separated", sweep_bytes_separated(dim, k, N, word))):
+        with vps.Context(dim, k, N, 1, vcycle_dtype=w["vcycle"], algorithm=alg) as ctx:
+            for _ in range(3):
+                ctx.smooth(0, u, b, sweeps=1)
+            ms = _median_ms(torch, lambda: ctx.smooth(0, u, b, sweeps=1))
+            out[alg] = {"sweep_ms": ms, "dof_per_s": n / (ms * 1e-3), "alg_bytes_per_sweep": nbytes,
+                        "alg_gbs": nbytes / (ms * 1e-3) / 1e9}
+            if alg == "combined":
+                Au = torch.empty_like(u)
+                for _ in range(3):
+                    ctx.apply(0, u, Au)
+                out["apply_ms"] = _median_ms(torch, lambda: ctx.apply(0, u, Au))
+    out["sweep_over_apply"] = out["combined"]["sweep_ms"] / out["apply_ms"]
+    out["separated_over_combined_time"] = out["separated"]["sweep_ms"] / out["combined"]["sweep_ms"]
+    out["separated_over_combined_alg_bytes"] = (out["separated"]["alg_bytes_per_sweep"] /
+                                                 out["combined"]["alg_bytes_per_sweep"])
+    return out
+
+
 def run_extras(torch, vps, vi):
     out = {}
+    print("[bench] sweep protocol (combined and separated), finest level", file=sys.stderr, flush=True)
+    out["sweep_protocol"] = run_sweep_protocol(torch, vps, vi)
     print("[bench] small workloads", file=sys.stderr, flush=True)
     for name in ("poisson2d_q2_n32", "poisson3d_q4_n32"):
         out[name], _ = _solve(torch, vps, vi, name)

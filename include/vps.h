@@ -67,6 +67,13 @@ typedef enum {
   VPS_COEF_CELL_LEARNED = 2    /* as 1, each FDM eigenmode scaled by a per-patch factor */
 } vps_coef;
 
+/* Smoother algorithm: the two colorized forms of Section 3.2. */
+typedef enum {
+  VPS_ALG_COMBINED = 0,  /* Algorithm 4: per color, each patch forms its local residual from its closure */
+  VPS_ALG_SEPARATED = 1  /* Algorithm 3: per color, the global residual b - A u, then the local solves;
+                            3D, rho = 1, degree 2..4 */
+} vps_algorithm;
+
 typedef struct {
   int dim;               /* 2 or 3 */
   int degree;            /* k, 1..4 */
@@ -85,6 +92,8 @@ typedef struct {
                             (for a transfer: on its coarse level), single-pass
                             tile kernels below; 0 = default (32), 1 = always;
                             must be >= 0 */
+  int algorithm;         /* vps_algorithm of every smoothing step (vps_smooth_color,
+                            vps_smooth, the V-cycle) */
 } vps_config;
 
 typedef struct {

@@ -26,6 +26,7 @@ struct Level {
   void* u = nullptr;  // V-cycle work vectors in the V-cycle dtype
   void* b = nullptr;
   void* r = nullptr;
+  void* sep_r = nullptr;  // separated smoother: global residual of a color step (FP64-sized, either dtype)
   double* rho64 = nullptr;  // per-cell coefficient
   float* rho32 = nullptr;
   float* scal = nullptr;    // learned per-patch eigenmode factors
@@ -354,6 +355,8 @@ vps_dtype vdt(const vps_context* c) { return (vps_dtype)c->cfg.vcycle_dtype; }
 
 // ---- level operations (dtype t) ----
 
+hipError_t do_operator(vps_context* c, int l, const void* u, const void* b, void* out, vps_dtype t);
+
 hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dtype t, int color) {
   const Level& L = c->lv[l];
   const int k = c->cfg.degree, d = c->cfg.dim, coef = c->cfg.coef;
@@ -383,6 +386,12 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   P.Te = L.Te.empty() ? nullptr : L.Te.data();
   P.To = L.Te.empty() ? nullptr : L.To.data();
   P.lam_int = L.lam_int.empty() ? nullptr : L.lam_int.data();
+  if (c->cfg.algorithm == VPS_ALG_SEPARATED) {
+    // Algorithm 3: global residual, then the local solves of the color's patches
+    hipError_t e = do_operator(c, l, u, b, L.sep_r, t);
+    if (e != hipSuccess) return e;
+    return dispatch_tk(t, k, [&]<typename T, int K>() { return vps::launch_patch_solve<T, K>(P, L.sep_r, c->stream); });
+  }
   if (!P.lam_int || !P.Te) P.pb = P.pb > 0 ? P.pb : -1;  // -1: generic kernel, automatic batch
   return dispatch_tkd(t, k, d, [&]<typename T, int K, int D>() { return vps::launch_patch_color<T, K, D>(P, c->stream); });
 }
@@ -590,6 +599,7 @@ void free_all(vps_context* c) {
     hipFree(L.u);
     hipFree(L.b);
     hipFree(L.r);
+    hipFree(L.sep_r);
     hipFree(L.rho64);
     hipFree(L.rho32);
     hipFree(L.scal);
@@ -640,6 +650,9 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.coef < VPS_COEF_CONST || C.coef > VPS_COEF_CELL_LEARNED) return VPS_E_ARG;
   if (C.patches_per_block != 0 && !vps::valid_patches_per_block(C.patches_per_block)) return VPS_E_UNSUPPORTED;
   if (C.stream_min_cells < 0) return VPS_E_ARG;
+  if (C.algorithm != VPS_ALG_COMBINED && C.algorithm != VPS_ALG_SEPARATED) return VPS_E_ARG;
+  if (C.algorithm == VPS_ALG_SEPARATED && (C.dim != 3 || C.coef != VPS_COEF_CONST || C.degree < 2))
+    return VPS_E_UNSUPPORTED;
   // every node index must fit in int on the kernels' inner indexing
   const double nodes = std::pow((double)(C.degree * C.n_cells + 1), C.dim);
   if (nodes > 2.0e9) return VPS_E_UNSUPPORTED;
@@ -669,6 +682,8 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
     if (chk(hipMalloc(&L.u, L.nodes * esize(t)), "hipMalloc")) return bail(VPS_E_NOMEM);
     if (chk(hipMalloc(&L.b, L.nodes * esize(t)), "hipMalloc")) return bail(VPS_E_NOMEM);
     if (chk(hipMalloc(&L.r, L.nodes * esize(t)), "hipMalloc")) return bail(VPS_E_NOMEM);
+    if (C.algorithm == VPS_ALG_SEPARATED && chk(hipMalloc(&L.sep_r, L.nodes * sizeof(double)), "hipMalloc"))
+      return bail(VPS_E_NOMEM);
     if (C.coef != VPS_COEF_CONST) {
       size_t cells = 1;
       for (int e = 0; e < C.dim; ++e) cells *= (size_t)L.ncell;

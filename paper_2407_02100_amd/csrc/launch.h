@@ -43,6 +43,9 @@ struct PatchLaunch {
 
 template <typename T, int K, int D>
 hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s);
+// Separated smoother (3D, constant coefficient): u_int += A_j^{-1} r_int on the patches of L.color.
+template <typename T, int K>
+hipError_t launch_patch_solve(const PatchLaunch& L, const void* r, hipStream_t s);
 
 struct TileLaunch {
   const void* in;

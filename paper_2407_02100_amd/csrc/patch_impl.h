@@ -2,6 +2,7 @@
 // by patch_k<K>.hip so that the degrees compile in parallel.
 #include "kernels.h"
 #include "patch_wave.h"
+#include "patch_solve.h"
 #include "launch.h"
 
 namespace vps {
@@ -103,6 +104,45 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
   }
 }
 
+template <typename T, int K>
+hipError_t launch_patch_solve(const PatchLaunch& L, const void* r, hipStream_t s) {
+  if constexpr (K < 2) {
+    return hipErrorInvalidValue;  // the even/odd fast diagonalization needs K >= 2
+  } else {
+    static_assert(sizeof(SolveArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
+    constexpr int Q = 2 * K - 1;
+    if (!L.Te || !L.To || !L.lam_int) return hipErrorInvalidValue;
+    SolveArgs<T, K> w;
+    w.u = (T*)L.u;
+    w.r = (const T*)r;
+    w.n1 = L.n1;
+    const int N = L.ncell;
+    for (int e = 0; e < 3; ++e) {
+      const int v0 = ((L.color >> e) & 1) ? 1 : 2;
+      w.v0[e] = v0;
+      w.np[e] = (v0 <= N - 1) ? (N - 1 - v0) / 2 + 1 : 0;
+      if (w.np[e] == 0) return hipSuccess;  // no patch of this color
+    }
+    w.npatch = (unsigned)w.np[0] * (unsigned)w.np[1] * (unsigned)w.np[2];
+    if ((unsigned long long)w.npatch * (unsigned)w.np[0] >= (1ull << 32) ||
+        (unsigned long long)w.npatch * (unsigned)w.np[1] >= (1ull << 32))
+      return hipErrorInvalidValue;
+    const unsigned long long vbytes = (unsigned long long)L.n1 * L.n1 * L.n1 * sizeof(T);
+    if (vbytes >= (1ull << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
+    w.vec_bytes = (unsigned)vbytes;
+    w.magic_x = (unsigned)((1ull << 32) / (unsigned)w.np[0] + 1);
+    w.magic_y = (unsigned)((1ull << 32) / (unsigned)w.np[1] + 1);
+    for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
+    for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
+    for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];
+    const unsigned grid = (w.npatch + kXcd - 1) / kXcd * kXcd;
+    patch_solve3_kernel<T, K><<<grid, 64, 0, s>>>(w);
+    return hipGetLastError();
+  }
+}
+
+template hipError_t launch_patch_solve<double, VPS_PATCH_K>(const PatchLaunch&, const void*, hipStream_t);
+template hipError_t launch_patch_solve<float, VPS_PATCH_K>(const PatchLaunch&, const void*, hipStream_t);
 template hipError_t launch_patch_color<double, VPS_PATCH_K, 2>(const PatchLaunch&, hipStream_t);
 template hipError_t launch_patch_color<double, VPS_PATCH_K, 3>(const PatchLaunch&, hipStream_t);
 template hipError_t launch_patch_color<float, VPS_PATCH_K, 2>(const PatchLaunch&, hipStream_t);

@@ -2,17 +2,19 @@
 
 Two steps:
 
-1. ``python -m paper_2407_02100_amd.traffic_probe run [--dtype f32|f64]``
+1. ``python -m paper_2407_02100_amd.traffic_probe run [--dtype f32|f64] [--algorithm combined|separated]``
    runs on the GPU, under ``rocprofv3 --pmc <COUNTER> --output-format csv``:
    one plain device-to-device copy of a known size (the calibration kernel),
    then one sweep of the smoother on the finest level of the 3D Q4 128^3
-   workload (8 color launches).
-2. ``python -m paper_2407_02100_amd.traffic_probe summarize FETCH_CSV WRITE_CSV``
+   workload (8 color steps: one kernel each for the combined form, a residual
+   and a solve kernel each for the separated form).
+2. ``python -m paper_2407_02100_amd.traffic_probe summarize FETCH_CSV WRITE_CSV [--out FILE]``
    reads the two counter files (FETCH_SIZE and WRITE_SIZE passes, in KiB per
    dispatch), scales each counter by the value it reads for the copy kernel
-   (bytes the copy must move / counter), and writes the bytes per smoother
-   launch to ``profiles/patch_sweep_traffic.json`` together with a hash of
-   the kernel sources (the number is void once the kernel changes).
+   (bytes the copy must move / counter), and writes the bytes per launch of
+   every smoother kernel and per sweep (by default to
+   ``profiles/patch_sweep_traffic.json``) together with a hash of the kernel
+   sources (the number is void once the kernel changes).
 """
 from __future__ import annotations
 
@@ -30,13 +32,13 @@ COPY_BYTES = 512 * 1024 * 1024  # bytes read by the calibration copy (and writte
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("patch_wave.h", "patch_impl.h"):
+    for f in ("patch_wave.h",):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def run(dtype: str, n_cells: int = 128, degree: int = 4):
+def run(dtype: str, n_cells: int = 128, degree: int = 4, algorithm: str = "combined"):
     if ROOT not in sys.path:
         sys.path.insert(0, ROOT)
     import torch
@@ -50,7 +52,7 @@ def run(dtype: str, n_cells: int = 128, degree: int = 4):
     del src, dst
     b = torch.from_numpy(vi.seeded_vector(3, degree, n_cells, 5)).to("cuda", tdt)
     u = torch.from_numpy(vi.seeded_vector(3, degree, n_cells, 105)).to("cuda", tdt)
-    with vps.Context(3, degree, n_cells, 1, vcycle_dtype=dtype) as ctx:
+    with vps.Context(3, degree, n_cells, 1, vcycle_dtype=dtype, algorithm=algorithm) as ctx:
         ctx.smooth(0, u, b, sweeps=1)
         ctx.sync()
     print("traffic probe done", flush=True)
@@ -68,26 +70,40 @@ def _read(path):
     return out
 
 
+SMOOTHER_KERNELS = ("patch_wave3_kernel", "patch_color_kernel", "patch_solve3_kernel", "stream3_kernel")
+
+
 def summarize(fetch_csv: str, write_csv: str, dtype: str, workload: str = "poisson3d_q4_n128",
               out_path: str | None = None):
-    res = {}
+    per = {}
+    scales = {}
     for label, path in (("fetch", fetch_csv), ("write", write_csv)):
         rows = _read(path)
         copy = [v for _, n, _, v in rows if "copyBuffer" in n or "copy" in n.lower() and "patch" not in n]
-        patch = [v for _, n, _, v in rows if "patch_wave3_kernel" in n or "patch_color_kernel" in n]
-        if not copy or not patch:
-            raise SystemExit(f"{path}: copy or smoother dispatches missing")
+        if not copy:
+            raise SystemExit(f"{path}: copy dispatch missing")
         kib_copy = max(copy)
         scale = COPY_BYTES / (kib_copy * 1024.0)  # bytes per counter KiB-unit
-        res[label] = {"copy_kib": kib_copy, "scale": scale,
-                      "patch_kib_per_launch": sum(patch) / len(patch),
-                      "patch_bytes_per_launch": sum(patch) / len(patch) * 1024.0 * scale,
-                      "launches": len(patch)}
-    total = res["fetch"]["patch_bytes_per_launch"] + res["write"]["patch_bytes_per_launch"]
+        scales[label] = {"copy_kib": kib_copy, "scale": scale}
+        for _, n, _, v in rows:
+            key = next((k for k in SMOOTHER_KERNELS if k in n), None)
+            if key:
+                per.setdefault(key, {}).setdefault(label, []).append(v * 1024.0 * scale)
+    if not per:
+        raise SystemExit("no smoother dispatches in the counter files")
+    kernels = {}
+    for key, d in per.items():
+        f, w = d.get("fetch", [0.0]), d.get("write", [0.0])
+        kernels[key] = {"launches": len(f), "fetch_bytes_per_launch": sum(f) / len(f),
+                        "write_bytes_per_launch": sum(w) / len(w)}
+    sweep = sum((v["fetch_bytes_per_launch"] + v["write_bytes_per_launch"]) * v["launches"] for v in kernels.values())
     doc = {"workload": workload, "dtype": dtype, "kernel_source_hash": kernel_source_hash(),
-           "bytes_per_launch": total, "fetch": res["fetch"], "write": res["write"],
+           "kernels": kernels, "bytes_per_sweep": sweep, "calibration": scales,
            "note": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE per dispatch, each scaled by the value the "
                    "same counter reads for a plain copy of 512 MiB in the same process"}
+    main = kernels.get("patch_wave3_kernel") or kernels.get("patch_color_kernel")
+    if main:
+        doc["bytes_per_launch"] = main["fetch_bytes_per_launch"] + main["write_bytes_per_launch"]
     out_path = out_path or os.path.join(ROOT, "profiles", "patch_sweep_traffic.json")
     with open(out_path, "w") as f:
         json.dump(doc, f, indent=1)
@@ -100,6 +116,7 @@ if __name__ == "__main__":
     sub = ap.add_subparsers(dest="cmd", required=True)
     r = sub.add_parser("run")
     r.add_argument("--dtype", default="f32")
+    r.add_argument("--algorithm", default="combined")
     s = sub.add_parser("summarize")
     s.add_argument("fetch_csv")
     s.add_argument("write_csv")
@@ -107,6 +124,6 @@ if __name__ == "__main__":
     s.add_argument("--out", default=None)
     a = ap.parse_args()
     if a.cmd == "run":
-        run(a.dtype)
+        run(a.dtype, algorithm=a.algorithm)
     else:
         summarize(a.fetch_csv, a.write_csv, a.dtype, out_path=a.out)
