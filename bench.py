@@ -177,6 +177,15 @@ def run_sweep_protocol(torch, vps, vi, name="poisson3d_q4_n128"):
                 for _ in range(3):
                     ctx.apply(0, u, Au)
                 out["apply_ms"] = _median_ms(torch, lambda: ctx.apply(0, u, Au))
+    # dispatch-order study: the order in which the workgroups of a color visit its patches
+    orders = {0: "lexicographic, one slab per XCD", 1: "lexicographic, round-robin over XCDs",
+              2: "Morton curve, one slab per XCD", 3: "4x4x4 tiles, one slab per XCD"}
+    out["patch_order_sweep_ms"] = {}
+    for order, label in orders.items():
+        with vps.Context(dim, k, N, 1, vcycle_dtype=w["vcycle"], patch_order=order) as ctx:
+            for _ in range(3):
+                ctx.smooth(0, u, b, sweeps=1)
+            out["patch_order_sweep_ms"][label] = _median_ms(torch, lambda: ctx.smooth(0, u, b, sweeps=1))
     out["sweep_over_apply"] = out["combined"]["sweep_ms"] / out["apply_ms"]
     out["separated_over_combined_time"] = out["separated"]["sweep_ms"] / out["combined"]["sweep_ms"]
     out["separated_over_combined_alg_bytes"] = (out["separated"]["alg_bytes_per_sweep"] /

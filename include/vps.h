@@ -94,6 +94,12 @@ typedef struct {
                             must be >= 0 */
   int algorithm;         /* vps_algorithm of every smoothing step (vps_smooth_color,
                             vps_smooth, the V-cycle) */
+  int patch_order;       /* 3D, rho = 1, one patch per wavefront: order in which the
+                            workgroups of a color visit its patches (dispatch-order
+                            study): 0 = lexicographic, one contiguous slab per XCD
+                            (default); 1 = lexicographic, dealt round-robin over
+                            the XCDs; 2 = Morton curve, one slab per XCD; 3 = tiles
+                            of 4x4x4 patches, one slab per XCD */
 } vps_config;
 
 typedef struct {

@@ -370,6 +370,7 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   P.color = color;
   P.coef = coef;
   P.pb = c->cfg.patches_per_block;  // 0: the launcher chooses
+  P.order = c->cfg.patch_order;
   if (coef == VPS_COEF_CONST) {
     P.M[0] = L.Mfull.data();
     P.M[1] = nullptr;
@@ -651,6 +652,7 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.patches_per_block != 0 && !vps::valid_patches_per_block(C.patches_per_block)) return VPS_E_UNSUPPORTED;
   if (C.stream_min_cells < 0) return VPS_E_ARG;
   if (C.algorithm != VPS_ALG_COMBINED && C.algorithm != VPS_ALG_SEPARATED) return VPS_E_ARG;
+  if (C.patch_order < 0 || C.patch_order > 3) return VPS_E_ARG;
   if (C.algorithm == VPS_ALG_SEPARATED && (C.dim != 3 || C.coef != VPS_COEF_CONST || C.degree < 2))
     return VPS_E_UNSUPPORTED;
   // every node index must fit in int on the kernels' inner indexing

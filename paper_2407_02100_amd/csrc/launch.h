@@ -39,6 +39,7 @@ struct PatchLaunch {
   const double* Te;    // K x K
   const double* To;    // (K-1) x (K-1)
   const double* lam_int;  // Q eigenvalues in the even/odd mode order (host), or null
+  int order;              // vps_config.patch_order (3D one-patch-per-wave kernel)
 };
 
 template <typename T, int K, int D>

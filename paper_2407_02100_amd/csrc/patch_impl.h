@@ -1,5 +1,7 @@
 // Launcher of the patch smoother kernel for one degree (VPS_PATCH_K), included
 // by patch_k<K>.hip so that the degrees compile in parallel.
+#include <algorithm>
+
 #include "kernels.h"
 #include "patch_wave.h"
 #include "patch_solve.h"
@@ -90,7 +92,26 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
       for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
       for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];
       // one wave per patch; the grid is padded to a multiple of the XCD count
-      const unsigned grid = (w.npatch + kXcd - 1) / kXcd * kXcd;
+      w.order = L.order;
+      w.cover_log2 = 0;
+      w.tiles_x = w.tiles_y = 1;
+      if (L.order <= 1) {
+        w.nslots = w.npatch;
+      } else if (L.order == 2) {
+        const int m = std::max(a.np[0], std::max(a.np[1], a.np[2]));
+        while ((1 << w.cover_log2) < m) ++w.cover_log2;
+        if (w.cover_log2 > 10) return hipErrorInvalidValue;
+        w.nslots = 1u << (3 * w.cover_log2);
+      } else if (L.order == 3) {
+        w.tiles_x = (a.np[0] + 3) / 4;
+        w.tiles_y = (a.np[1] + 3) / 4;
+        const unsigned long long slots = 64ull * w.tiles_x * w.tiles_y * ((a.np[2] + 3) / 4);
+        if (slots >= (1ull << 31)) return hipErrorInvalidValue;
+        w.nslots = (unsigned)slots;
+      } else {
+        return hipErrorInvalidValue;
+      }
+      const unsigned grid = (w.nslots + kXcd - 1) / kXcd * kXcd;
       patch_wave3_kernel<T, K><<<grid, 64, 0, s>>>(w);
       return hipGetLastError();
     }

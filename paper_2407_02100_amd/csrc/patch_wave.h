@@ -111,6 +111,13 @@ struct WaveArgs {
   // exact division by np[0] and np[1] for dividends below 2^32 / divisor:
   // n / d = umulhi(n, floor(2^32 / d) + 1)
   unsigned magic_x, magic_y;
+  // order in which the workgroups visit the color's patches (dispatch-order study):
+  // 0 lexicographic in one slab per XCD, 1 lexicographic dealt round-robin over the XCDs,
+  // 2 Morton curve over a 2^cover_log2 cube in one slab per XCD, 3 tiles of 4^3 patches in one slab per XCD
+  int order;
+  int cover_log2;
+  unsigned nslots;  // workgroups of the launch that map to a position (before the range check)
+  int tiles_x, tiles_y;
   T M[(2 * K - 1) * (2 * K + 1)];    // interior rows of the 2-cell patch mass matrix
   T Kst[(2 * K - 1) * (2 * K + 1)];  // ... and stiffness matrix
   WaveFdm<T, K> f;
@@ -168,15 +175,37 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
 
   const unsigned h = blockIdx.x;
   const unsigned per = gridDim.x / kXcd;
-  const unsigned logical = (h % kXcd) * per + h / kXcd;
-  if (logical >= a.npatch) return;
+  const unsigned logical = (a.order == 1) ? h : (h % kXcd) * per + h / kXcd;
+  if (logical >= a.nslots) return;
   const int lane = threadIdx.x;
   const unsigned npx = (unsigned)a.np[0], npy = (unsigned)a.np[1];
-  const unsigned qx = __umulhi(logical, a.magic_x);
-  const unsigned qy = __umulhi(qx, a.magic_y);
-  const int px = (int)(logical - qx * npx);
-  const int py = (int)(qx - qy * npy);
-  const int pz = (int)qy;
+  int px, py, pz;
+  if (a.order <= 1) {
+    const unsigned qx = __umulhi(logical, a.magic_x);
+    const unsigned qy = __umulhi(qx, a.magic_y);
+    px = (int)(logical - qx * npx);
+    py = (int)(qx - qy * npy);
+    pz = (int)qy;
+  } else if (a.order == 2) {
+    auto compact = [](unsigned m) {  // every third bit
+      m &= 0x09249249u;
+      m = (m ^ (m >> 2)) & 0x030c30c3u;
+      m = (m ^ (m >> 4)) & 0x0300f00fu;
+      m = (m ^ (m >> 8)) & 0xff0000ffu;
+      m = (m ^ (m >> 16)) & 0x000003ffu;
+      return m;
+    };
+    px = (int)compact(logical);
+    py = (int)compact(logical >> 1);
+    pz = (int)compact(logical >> 2);
+  } else {
+    const unsigned t = logical >> 6, in = logical & 63u;
+    const unsigned tx = t % (unsigned)a.tiles_x, tr = t / (unsigned)a.tiles_x;
+    px = (int)(4 * tx + (in & 3u));
+    py = (int)(4 * (tr % (unsigned)a.tiles_y) + ((in >> 2) & 3u));
+    pz = (int)(4 * (tr / (unsigned)a.tiles_y) + (in >> 4));
+  }
+  if (px >= a.np[0] || py >= a.np[1] || pz >= a.np[2]) return;
   const unsigned n1 = (unsigned)a.n1;
   const size_t n2 = (size_t)n1 * n1;
   const size_t base = (size_t)(K * (a.v0[0] + 2 * px - 1)) + (size_t)n1 * (size_t)(K * (a.v0[1] + 2 * py - 1)) +

@@ -38,7 +38,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def run(dtype: str, n_cells: int = 128, degree: int = 4, algorithm: str = "combined"):
+def run(dtype: str, n_cells: int = 128, degree: int = 4, algorithm: str = "combined", order: int = 0):
     if ROOT not in sys.path:
         sys.path.insert(0, ROOT)
     import torch
@@ -52,7 +52,7 @@ def run(dtype: str, n_cells: int = 128, degree: int = 4, algorithm: str = "combi
     del src, dst
     b = torch.from_numpy(vi.seeded_vector(3, degree, n_cells, 5)).to("cuda", tdt)
     u = torch.from_numpy(vi.seeded_vector(3, degree, n_cells, 105)).to("cuda", tdt)
-    with vps.Context(3, degree, n_cells, 1, vcycle_dtype=dtype, algorithm=algorithm) as ctx:
+    with vps.Context(3, degree, n_cells, 1, vcycle_dtype=dtype, algorithm=algorithm, patch_order=order) as ctx:
         ctx.smooth(0, u, b, sweeps=1)
         ctx.sync()
     print("traffic probe done", flush=True)
@@ -117,6 +117,7 @@ if __name__ == "__main__":
     r = sub.add_parser("run")
     r.add_argument("--dtype", default="f32")
     r.add_argument("--algorithm", default="combined")
+    r.add_argument("--order", type=int, default=0, help="vps_config.patch_order")
     s = sub.add_parser("summarize")
     s.add_argument("fetch_csv")
     s.add_argument("write_csv")
@@ -124,6 +125,6 @@ if __name__ == "__main__":
     s.add_argument("--out", default=None)
     a = ap.parse_args()
     if a.cmd == "run":
-        run(a.dtype, algorithm=a.algorithm)
+        run(a.dtype, algorithm=a.algorithm, order=a.order)
     else:
         summarize(a.fetch_csv, a.write_csv, a.dtype, out_path=a.out)
