@@ -193,8 +193,45 @@ def run_sweep_protocol(torch, vps, vi, name="poisson3d_q4_n128"):
     return out
 
 
+# The paper's table of multigrid timings (32 CPU cores, FP64, residual reduction 1e-12): smoothing and
+# vmult time per application, iterations, solve time; context for the same shapes on one MI355X.
+PAPER_TABLE = {
+    "paper2d_q3_n2048": {"smoothing_s": 0.197856, "vmult_s": 0.034349, "iterations": 6, "solve_s": 12.0369},
+    "paper2d_q5_n2048": {"smoothing_s": 0.387558, "vmult_s": 0.0812562, "iterations": 5, "solve_s": 23.3042},
+    "paper3d_q5_n128": {"smoothing_s": 2.37646, "vmult_s": 0.213686, "iterations": 6, "solve_s": 115.17},
+}
+
+
+def run_paper_workloads(torch, vps, vi):
+    out = {}
+    for name, paper in PAPER_TABLE.items():
+        w = vi.WORKLOADS[name]
+        dim, k, N = w["dim"], w["degree"], w["n_cells"]
+        print(f"[bench] paper shape {name}", file=sys.stderr, flush=True)
+        b = torch.from_numpy(vi.seeded_vector(dim, k, N, w["rhs_seed"])).to("cuda")
+        u = torch.from_numpy(vi.seeded_vector(dim, k, N, w["u0_seed"])).to("cuda")
+        x = torch.empty_like(b)
+        Au = torch.empty_like(b)
+        with vps.Context(dim, k, N, w["levels"], w["pre"], w["post"], vcycle_dtype=w["vcycle"]) as ctx:
+            L = w["levels"] - 1
+            ctx.smooth(L, u, b, sweeps=1)
+            sweep_ms = _median_ms(torch, lambda: ctx.smooth(L, u, b, sweeps=1), reps=3, inner=3)
+            ctx.apply(L, u, Au)
+            vmult_ms = _median_ms(torch, lambda: ctx.apply(L, u, Au), reps=3, inner=5)
+            ctx.solve(b, x, rtol=1e-12, maxit=100)
+            info = ctx.solve(b, x, rtol=1e-12, maxit=100)
+        n = b.numel()
+        out[name] = {"nodes": n, "smoothing_s": sweep_ms * 1e-3, "vmult_s": vmult_ms * 1e-3,
+                     "iterations": info["iterations"], "solve_s": info["seconds"],
+                     "rel_residual_true": info["rel_residual_true"],
+                     "smoother_dof_per_s": n / (sweep_ms * 1e-3), "paper_cpu_32_cores": paper}
+        del b, u, x, Au
+    return out
+
+
 def run_extras(torch, vps, vi):
     out = {}
+    out["paper_shapes_fp64"] = run_paper_workloads(torch, vps, vi)
     print("[bench] sweep protocol (combined and separated), finest level", file=sys.stderr, flush=True)
     out["sweep_protocol"] = run_sweep_protocol(torch, vps, vi)
     print("[bench] small workloads", file=sys.stderr, flush=True)

@@ -76,7 +76,8 @@ typedef enum {
 
 typedef struct {
   int dim;               /* 2 or 3 */
-  int degree;            /* k, 1..4 */
+  int degree;            /* k, 1..5 (5: 3D smoother on the generic kernel, 3D operator and
+                            transfers always on the streaming kernels) */
   int n_cells;           /* N on the finest level; divisible by 2^(n_levels-1) */
   int n_levels;          /* 1..16; coarsest level must have >= 2 cells per direction */
   int pre_sweeps;        /* forward sweeps before the coarse correction, >= 0 */
@@ -116,7 +117,7 @@ typedef struct {
  * matrices, the coarse solver) on the host in FP64 and uploads them, and
  * allocates the V-cycle work vectors of every level in cfg->vcycle_dtype.
  * hip_stream: a hipStream_t (may be NULL for the null stream).
- * Returns VPS_E_UNSUPPORTED for degree outside 1..4, dim outside {2,3},
+ * Returns VPS_E_UNSUPPORTED for degree outside 1..5, dim outside {2,3},
  * N not divisible by 2^(n_levels-1) or a coarsest level below 2 cells.
  * A context whose coarsest grid is too large for the coarse solver (rho = 1:
  * more than 15 free nodes per direction in 3D, 63 in 2D; cell coefficient:

@@ -126,6 +126,7 @@ hipError_t dispatch_kd(int k, int d, F& f) {
 #define VPS_KD(KK, DD) \
   if (k == KK && d == DD) return f.template operator()<T, KK, DD>();
   VPS_KD(1, 2) VPS_KD(1, 3) VPS_KD(2, 2) VPS_KD(2, 3) VPS_KD(3, 2) VPS_KD(3, 3) VPS_KD(4, 2) VPS_KD(4, 3)
+  VPS_KD(5, 2) VPS_KD(5, 3)
 #undef VPS_KD
   return hipErrorInvalidValue;
 }
@@ -143,6 +144,7 @@ hipError_t dispatch_k(int k, F& f) {
     case 2: return f.template operator()<T, 2>();
     case 3: return f.template operator()<T, 3>();
     case 4: return f.template operator()<T, 4>();
+    case 5: return f.template operator()<T, 5>();
   }
   return hipErrorInvalidValue;
 }
@@ -349,7 +351,10 @@ hipError_t upload(const std::vector<double>& src, void** dst, hipStream_t s) {
 bool level_ok(const vps_context* c, int l) { return c && l >= 0 && l < (int)c->lv.size(); }
 
 // cells per direction from which the plane-streaming kernels are used
-int stream_min(const vps_context* c) { return c->cfg.stream_min_cells > 0 ? c->cfg.stream_min_cells : 32; }
+int stream_min(const vps_context* c) {
+  if (c->cfg.dim == 3 && c->cfg.degree == 5) return 1;  // the single-pass 3D tiles exceed the LDS at k = 5
+  return c->cfg.stream_min_cells > 0 ? c->cfg.stream_min_cells : 32;
+}
 
 vps_dtype vdt(const vps_context* c) { return (vps_dtype)c->cfg.vcycle_dtype; }
 
@@ -641,7 +646,7 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   *out = nullptr;
   const vps_config& C = *cfg;
   if (C.dim != 2 && C.dim != 3) return VPS_E_UNSUPPORTED;
-  if (C.degree < 1 || C.degree > 4) return VPS_E_UNSUPPORTED;
+  if (C.degree < 1 || C.degree > 5) return VPS_E_UNSUPPORTED;
   if (C.n_levels < 1 || C.n_cells < 2) return VPS_E_UNSUPPORTED;
   if (C.n_levels > VPS_MAX_LEVELS || C.n_cells % (1 << (C.n_levels - 1)) != 0) return VPS_E_UNSUPPORTED;
   const int n0 = C.n_cells >> (C.n_levels - 1);
@@ -653,7 +658,7 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.stream_min_cells < 0) return VPS_E_ARG;
   if (C.algorithm != VPS_ALG_COMBINED && C.algorithm != VPS_ALG_SEPARATED) return VPS_E_ARG;
   if (C.patch_order < 0 || C.patch_order > 3) return VPS_E_ARG;
-  if (C.algorithm == VPS_ALG_SEPARATED && (C.dim != 3 || C.coef != VPS_COEF_CONST || C.degree < 2))
+  if (C.algorithm == VPS_ALG_SEPARATED && (C.dim != 3 || C.coef != VPS_COEF_CONST || C.degree < 2 || C.degree > 4))
     return VPS_E_UNSUPPORTED;
   // every node index must fit in int on the kernels' inner indexing
   const double nodes = std::pow((double)(C.degree * C.n_cells + 1), C.dim);

@@ -12,7 +12,7 @@
 namespace vps {
 
 // Tile sizes (cells per direction) of the operator and transfer kernels.
-constexpr int op_tc(int K, int D) { return D == 2 ? (K <= 2 ? 4 : 2) : (K == 1 ? 8 : (K == 2 ? 4 : 2)); }
+constexpr int op_tc(int K, int D) { return D == 2 ? (K <= 2 ? 4 : 2) : (K == 1 ? 8 : (K == 2 ? 4 : (K <= 4 ? 2 : 1))); }
 constexpr int restrict_tc(int K, int D) { return D == 2 ? 2 : (K <= 2 ? 2 : 1); }
 constexpr int prolong_tc(int K, int D) { return D == 2 ? 2 : (K <= 2 ? 2 : 1); }
 

@@ -64,7 +64,7 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
   for (int i = 0; i < Q * Q; ++i) a.m.T1[i] = (T)L.T1[i];
   for (int i = 0; i < Q; ++i) a.m.lam[i] = (T)L.lam[i];
   if (D == 3 && L.coef == 0 && L.pb == 0) {
-    if constexpr (K >= 2) {
+    if constexpr (K >= 2 && K <= 4) {  // (2K-1)^2 interior lines must fit the 64 lanes of a wave
       static_assert(sizeof(WaveArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
       WaveArgs<T, K> w;
       w.u = a.u;
@@ -127,8 +127,8 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
 
 template <typename T, int K>
 hipError_t launch_patch_solve(const PatchLaunch& L, const void* r, hipStream_t s) {
-  if constexpr (K < 2) {
-    return hipErrorInvalidValue;  // the even/odd fast diagonalization needs K >= 2
+  if constexpr (K < 2 || K > 4) {
+    return hipErrorInvalidValue;  // even/odd FDM needs K >= 2; one wave per patch needs (2K-1)^2 <= 64
   } else {
     static_assert(sizeof(SolveArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
     constexpr int Q = 2 * K - 1;

@@ -73,6 +73,8 @@ hipError_t launch_stream_prolong(const StreamLaunch& L, hipStream_t s) {
   template hipError_t launch_stream_restrict<T, K>(const StreamLaunch&, hipStream_t);  \
   template hipError_t launch_stream_prolong<T, K>(const StreamLaunch&, hipStream_t);
 VPS_STREAM_INST(double, 1) VPS_STREAM_INST(double, 2) VPS_STREAM_INST(double, 3) VPS_STREAM_INST(double, 4)
+VPS_STREAM_INST(double, 5)
 VPS_STREAM_INST(float, 1) VPS_STREAM_INST(float, 2) VPS_STREAM_INST(float, 3) VPS_STREAM_INST(float, 4)
+VPS_STREAM_INST(float, 5)
 
 }  // namespace vps

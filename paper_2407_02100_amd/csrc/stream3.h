@@ -46,10 +46,10 @@ struct StreamShape {
   static constexpr int PO = PR ? 2 * K : K;
   static constexpr int PI = (KIND == STREAM_RESTRICT) ? 2 * K : K;
   static constexpr int W = OP ? 2 * K + 1 : PR ? K + 1 : 4 * K + 1;
-  static constexpr int TX = PR ? ((K == 1) ? 16 : (K == 2) ? 8 : (K == 3) ? 5 : 4)
-                               : ((K == 1) ? 32 : (K == 2) ? 16 : 8);
+  static constexpr int TX = PR ? ((K == 1) ? 16 : (K == 2) ? 8 : (K == 3) ? 5 : (K == 4) ? 4 : 3)
+                               : ((K == 1) ? 32 : (K == 2) ? 16 : (K <= 4) ? 8 : 6);
   static constexpr int TY = PR ? ((K == 1) ? 32 : (K == 2) ? 16 : 8)
-                               : ((K == 1) ? 32 : (K == 2) ? 16 : (K == 3) ? 10 : 8);
+                               : ((K == 1) ? 32 : (K == 2) ? 16 : (K == 3) ? 10 : (K == 4) ? 8 : (OP ? 8 : 4));
   static constexpr int NA = OP ? 2 : 1;  // arrays after the x contraction
   static constexpr int ZIN = (KIND == STREAM_RESTRICT) ? 2 * K : K;
   static constexpr int ZO = PR ? 2 * K : K + 1;

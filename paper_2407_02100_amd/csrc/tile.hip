@@ -11,7 +11,9 @@ template <typename T, int KIND, int K, int D, int TC>
 hipError_t go_tile(const TileLaunch& L, hipStream_t s) {
   using Sh = TileShape<KIND, K, TC>;
   using KS = TileKernelShape<T, KIND, K, D, TC>;
-  static_assert((KS::BUF0 + KS::BUF1) * sizeof(T) <= 65536, "tile does not fit the workgroup LDS");
+  if constexpr ((KS::BUF0 + KS::BUF1) * sizeof(T) > 65536) {
+    return hipErrorInvalidValue;  // this tile does not fit the workgroup LDS (3D, k = 5: streaming kernels only)
+  } else {
   static_assert(sizeof(TileArgs<T, KIND, K, TC>) <= 4096, "kernel arguments exceed 4 KiB");
   TileArgs<T, KIND, K, TC> a;
   a.in = (const T*)L.in;
@@ -25,6 +27,7 @@ hipError_t go_tile(const TileLaunch& L, hipStream_t s) {
   dim3 grid(L.tiles, L.tiles, D == 3 ? L.tiles : 1);
   tile_kernel<T, KIND, K, D, TC><<<grid, kBlock, 0, s>>>(a);
   return hipGetLastError();
+  }
 }
 
 template <typename T, int K, int D>
@@ -145,6 +148,7 @@ VPS_TILE_INST_K(1)
 VPS_TILE_INST_K(2)
 VPS_TILE_INST_K(3)
 VPS_TILE_INST_K(4)
+VPS_TILE_INST_K(5)
 
 // ---- patch shape helpers ----
 template <typename T, int K, int D, int COEF>
@@ -168,7 +172,7 @@ static int patch_lds_bytes(int K, int D, int coef, int pb, bool fp64) {
 #define VPS_LDS_CASE(KK, DD)                                                                  \
   if (K == KK && D == DD) return fp64 ? lds_coef<double, KK, DD>(coef, pb) : lds_coef<float, KK, DD>(coef, pb);
   VPS_LDS_CASE(1, 2) VPS_LDS_CASE(1, 3) VPS_LDS_CASE(2, 2) VPS_LDS_CASE(2, 3)
-  VPS_LDS_CASE(3, 2) VPS_LDS_CASE(3, 3) VPS_LDS_CASE(4, 2) VPS_LDS_CASE(4, 3)
+  VPS_LDS_CASE(3, 2) VPS_LDS_CASE(3, 3) VPS_LDS_CASE(4, 2) VPS_LDS_CASE(4, 3) VPS_LDS_CASE(5, 2) VPS_LDS_CASE(5, 3)
 #undef VPS_LDS_CASE
   return 1 << 30;
 }

@@ -46,7 +46,7 @@ def test_status_strings(lib):
 
 @pytest.mark.parametrize("cfg,status", [
     (dict(dim=4, degree=2, n_cells=8, n_levels=2), -2),
-    (dict(dim=3, degree=5, n_cells=8, n_levels=2), -2),
+    (dict(dim=3, degree=6, n_cells=8, n_levels=2), -2),
     (dict(dim=3, degree=2, n_cells=12, n_levels=4), -2),   # 12 not divisible by 8
     (dict(dim=3, degree=2, n_cells=8, n_levels=4), -2),    # coarsest level has 1 cell
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_block=3), -2),

@@ -116,3 +116,21 @@ def test_stationary_iteration_converges(vps):
         u = torch.zeros(b.size, dtype=torch.float64, device="cuda")
         hist = ctx.vcycle_iterate(dev(b), u, 8)
     assert rel(np.array(hist), np.array(hist_or)) <= 1e-6
+
+
+@pytest.mark.parametrize("dim,k,N,L", [(2, 5, 16, 4), (3, 5, 8, 3)])
+def test_solve_degree5(vps, dim, k, N, L):
+    """Q5 (the paper's element) down to a single-patch coarse grid (2 cells per direction)."""
+    say("solve Q5", dim, N, L)
+    b = vi.seeded_vector(dim, k, N, 71)
+    import torch
+    with vps.Context(dim, k, N, L) as ctx:
+        x = torch.empty(b.size, dtype=torch.float64, device="cuda")
+        info = ctx.solve(dev(b), x, rtol=1e-10, maxit=60)
+        xs = host(x)
+    assert info["rel_residual_true"] <= 1e-10
+    assert _recheck(dim, k, N, b, xs) <= 1e-10
+    if dim == 2:
+        H = multigrid.Hierarchy(dim, k, N, L)
+        xo, ito, _ = multigrid.pcg(H, b, 1e-10)
+        assert abs(ito - info["iterations"]) <= 1

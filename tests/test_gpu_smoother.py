@@ -9,7 +9,8 @@ from tests.gpu_util import dev, host, rel, say
 pytestmark = pytest.mark.gpu
 
 # sizes chosen so that the colors have ragged batches along x (5 and 4 patches etc.)
-CASES = [(2, 1, 10), (2, 2, 11), (2, 3, 10), (2, 4, 9), (3, 1, 9), (3, 2, 7), (3, 3, 5), (3, 4, 5)]
+CASES = [(2, 1, 10), (2, 2, 11), (2, 3, 10), (2, 4, 9), (2, 5, 7), (3, 1, 9), (3, 2, 7), (3, 3, 5), (3, 4, 5),
+         (3, 5, 4)]
 
 
 @pytest.fixture(scope="module")
@@ -107,7 +108,8 @@ def test_apply_and_residual(vps, dim, k, N):
         assert rel(host(out), b - A @ u0) <= 1e-13
 
 
-@pytest.mark.parametrize("dim,k,Nc", [(2, 1, 5), (2, 2, 3), (2, 4, 3), (3, 1, 3), (3, 2, 3), (3, 3, 2), (3, 4, 2)])
+@pytest.mark.parametrize("dim,k,Nc", [(2, 1, 5), (2, 2, 3), (2, 4, 3), (2, 5, 3), (3, 1, 3), (3, 2, 3), (3, 3, 2),
+                                      (3, 4, 2), (3, 5, 2)])
 def test_transfers(vps, dim, k, Nc):
     say("transfer", dim, k, Nc)
     P = transfer.prolongation(dim, k, Nc)
@@ -124,7 +126,7 @@ def test_transfers(vps, dim, k, Nc):
         assert rel(host(u), uf + P @ ec) <= 1e-13
 
 
-@pytest.mark.parametrize("dim,k,N0", [(2, 2, 4), (2, 4, 8), (3, 2, 4), (3, 4, 4), (3, 3, 4)])
+@pytest.mark.parametrize("dim,k,N0", [(2, 2, 4), (2, 4, 8), (3, 2, 4), (3, 4, 4), (3, 3, 4), (2, 5, 4), (3, 5, 2)])
 def test_coarse_solve(vps, dim, k, N0):
     say("coarse", dim, k, N0)
     A = assemble.assemble(dim, k, N0)

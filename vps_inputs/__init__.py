@@ -110,4 +110,12 @@ WORKLOADS = {
                              rho_seed=4, train_seed_base=1000, train_patches=200_000),
     "poisson3d_q4_n128": dict(dim=3, degree=4, n_cells=128, levels=6, pre=2, post=2,
                               vcycle="f32", coef="const", rhs_seed=5, u0_seed=105),
+    # the paper's own shapes (Poisson, a single 2^d-cell patch refined 10 times in 2D and 6 times
+    # in 3D; multigrid down to that patch), FP64 as in the paper
+    "paper2d_q3_n2048": dict(dim=2, degree=3, n_cells=2048, levels=11, pre=1, post=1,
+                             vcycle="f64", coef="const", rhs_seed=11, u0_seed=111),
+    "paper2d_q5_n2048": dict(dim=2, degree=5, n_cells=2048, levels=11, pre=1, post=1,
+                             vcycle="f64", coef="const", rhs_seed=12, u0_seed=112),
+    "paper3d_q5_n128": dict(dim=3, degree=5, n_cells=128, levels=7, pre=1, post=1,
+                            vcycle="f64", coef="const", rhs_seed=13, u0_seed=113),
 }
