@@ -44,19 +44,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def color_counts(dim: int, k: int, n: int):
+def color_counts(dim: int, k: int, n: int, vlo: int = 1, vhi: int | None = None):
     """Per color: (closure nodes of the color's patches, interior nodes written).
 
     A color's patches sit at vertices v with fixed parity per direction; their
     closures [k(v-1), k(v+1)] tile a contiguous node range per direction and
-    their interiors hold (2k-1) nodes per direction each.
+    their interiors hold (2k-1) nodes per direction each.  [vlo, vhi] limits
+    the vertices of the slowest direction (one batch of the batched sweep).
     """
+    vhi = n - 1 if vhi is None else vhi
     out = []
     for color in range(2 ** dim):
         clo, inner = 1, 1
         for e in range(dim):
-            v0 = 1 if (color >> e) & 1 else 2
-            npat = (n - 1 - v0) // 2 + 1 if v0 <= n - 1 else 0
+            par = (color >> e) & 1
+            lo, hi = (vlo, vhi) if e == dim - 1 else (1, n - 1)
+            v0 = lo + ((lo & 1) != par)
+            npat = (hi - v0) // 2 + 1 if v0 <= hi else 0
             vlast = v0 + 2 * (npat - 1)
             clo *= (k * (vlast - v0 + 2) + 1) if npat > 0 else 0
             inner *= (2 * k - 1) * npat
@@ -64,9 +68,22 @@ def color_counts(dim: int, k: int, n: int):
     return out
 
 
-def sweep_bytes(dim: int, k: int, n: int, word: int) -> int:
-    """Algorithmic bytes of one sweep: per color read the closures of u, read b and write u on the interiors."""
-    return sum((clo + 2 * inner) * word for clo, inner in color_counts(dim, k, n))
+def batches(n: int, batch_layers: int):
+    """Vertex ranges [lo, hi] of the batches in the slowest direction (one range: whole colors)."""
+    if batch_layers <= 0 or n - 1 <= batch_layers:
+        return [(1, n - 1)]
+    return [(1 + i * batch_layers, min(n - 1, (i + 1) * batch_layers)) for i in range((n - 2) // batch_layers + 1)]
+
+
+def sweep_bytes(dim: int, k: int, n: int, word: int, batch_layers: int = 0) -> int:
+    """Algorithmic bytes of one sweep: per color (and batch) read the closures of u, read b and write u on
+    the interiors; a batched sweep reads the closure planes shared by neighbouring batches twice."""
+    return sum((clo + 2 * inner) * word for lo, hi in batches(n, batch_layers)
+               for clo, inner in color_counts(dim, k, n, lo, hi))
+
+
+def launches_per_sweep(dim: int, n: int, batch_layers: int = 0) -> int:
+    return sum(1 for lo, hi in batches(n, batch_layers) for clo, inner in color_counts(dim, 1, n, lo, hi) if inner)
 
 
 def sweep_bytes_separated(dim: int, k: int, n: int, word: int) -> int:
@@ -180,12 +197,28 @@ def run_sweep_protocol(torch, vps, vi, name="poisson3d_q4_n128"):
     # dispatch-order study: the order in which the workgroups of a color visit its patches
     orders = {0: "lexicographic, one slab per XCD", 1: "lexicographic, round-robin over XCDs",
               2: "Morton curve, one slab per XCD", 3: "4x4x4 tiles, one slab per XCD"}
+    bl = w.get("batch_layers", 0)
+    if bl:
+        with vps.Context(dim, k, N, 1, vcycle_dtype=w["vcycle"], batch_layers=bl) as ctx:
+            for _ in range(3):
+                ctx.smooth(0, u, b, sweeps=1)
+            ms = _median_ms(torch, lambda: ctx.smooth(0, u, b, sweeps=1))
+        nbytes = sweep_bytes(dim, k, N, word, bl)
+        out["combined_batched"] = {"batch_layers": bl, "sweep_ms": ms, "dof_per_s": n / (ms * 1e-3),
+                                   "alg_bytes_per_sweep": nbytes, "alg_gbs": nbytes / (ms * 1e-3) / 1e9}
     out["patch_order_sweep_ms"] = {}
     for order, label in orders.items():
         with vps.Context(dim, k, N, 1, vcycle_dtype=w["vcycle"], patch_order=order) as ctx:
             for _ in range(3):
                 ctx.smooth(0, u, b, sweeps=1)
             out["patch_order_sweep_ms"][label] = _median_ms(torch, lambda: ctx.smooth(0, u, b, sweeps=1))
+    # batch processing (Algorithm 5): slabs of B vertex layers, all colors of a slab in turn
+    out["batch_layers_sweep_ms"] = {}
+    for bl in (2, 4, 8, 16, 32):
+        with vps.Context(dim, k, N, 1, vcycle_dtype=w["vcycle"], batch_layers=bl) as ctx:
+            for _ in range(3):
+                ctx.smooth(0, u, b, sweeps=1)
+            out["batch_layers_sweep_ms"][str(bl)] = _median_ms(torch, lambda: ctx.smooth(0, u, b, sweeps=1))
     out["sweep_over_apply"] = out["combined"]["sweep_ms"] / out["apply_ms"]
     out["separated_over_combined_time"] = out["separated"]["sweep_ms"] / out["combined"]["sweep_ms"]
     out["separated_over_combined_alg_bytes"] = (out["separated"]["alg_bytes_per_sweep"] /
@@ -328,7 +361,8 @@ def main():
     copy_gbs = 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
 
-    ctx = vps.Context(dim, k, N, w["levels"], w["pre"], w["post"], vcycle_dtype=w["vcycle"])
+    bl = w.get("batch_layers", 0)
+    ctx = vps.Context(dim, k, N, w["levels"], w["pre"], w["post"], vcycle_dtype=w["vcycle"], batch_layers=bl)
     print(f"[bench] warmup {args.warmup} solves", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         ctx.solve(b, x, rtol=1e-10, maxit=100)
@@ -348,21 +382,25 @@ def main():
     sweeps = tim["smooth_sweeps"][L]
     t_sm = tim["smooth_s"][L]
     value = n * sweeps / t_sm
-    launches = sweeps * 2 ** dim
-    bytes_sweep = sweep_bytes(dim, k, N, word)
+    # one launch per (batch, color) on the finest level
+    lps = launches_per_sweep(dim, N, bl)
+    launches = sweeps * lps
+    bytes_sweep = sweep_bytes(dim, k, N, word, bl)
     per_launch_s = t_sm / launches
-    achieved = bytes_sweep / 2 ** dim / per_launch_s / 1e9
+    achieved = bytes_sweep / lps / per_launch_s / 1e9
 
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("workload") == args.workload:
+        if (tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("workload") == args.workload
+                and tr.get("batch_layers", 0) == bl):
             traffic = tr.get("bytes_per_launch")
 
     f64 = None
     if not args.no_f64_reference and w["vcycle"] == "f32":
         print("[bench] plain FP64 reference solve", file=sys.stderr, flush=True)
-        ctx64 = vps.Context(dim, k, N, w["levels"], w["pre"], w["post"], vcycle_dtype="f64")
+        bl64 = w.get("batch_layers_f64", bl)
+        ctx64 = vps.Context(dim, k, N, w["levels"], w["pre"], w["post"], vcycle_dtype="f64", batch_layers=bl64)
         ctx64.solve(b, x, rtol=1e-10, maxit=100)
         ctx64.timing_enable(True)
         i64 = ctx64.solve(b, x, rtol=1e-10, maxit=100)
@@ -371,7 +409,8 @@ def main():
         f64 = {"solve_s": i64["seconds"], "iterations": i64["iterations"],
                "rel_residual_true": i64["rel_residual_true"],
                "smoother_dof_per_s": n * t64["smooth_sweeps"][L] / t64["smooth_s"][L],
-               "smoother_gbs": sweep_bytes(dim, k, N, 8) * t64["smooth_sweeps"][L] / t64["smooth_s"][L] / 1e9}
+               "smoother_gbs": sweep_bytes(dim, k, N, 8, bl64) * t64["smooth_sweeps"][L] / t64["smooth_s"][L] / 1e9,
+               "batch_layers": bl64}
 
     extras = {} if args.no_extras else run_extras(torch, vps, vi)
 
@@ -395,7 +434,8 @@ def main():
                    "problem": f"-Laplace(u)=f on [0,1]^{dim}, Q{k}, {N}^{dim} cells, {n} nodes",
                    "levels": w["levels"], "cycle": f"V({w['pre']},{w['post']})",
                    "vcycle_dtype": w["vcycle"], "outer": "FP64 flexible CG" if w["vcycle"] == "f32" else "FP64 PCG",
-                   "rtol": 1e-10, "rhs": f"uniform [-1,1] on free nodes, seed {w['rhs_seed']}"},
+                   "rtol": 1e-10, "rhs": f"uniform [-1,1] on free nodes, seed {w['rhs_seed']}",
+                   "batch_layers": bl},
         "solve": {"seconds": solve_s, "iterations": infos[-1]["iterations"],
                   "rel_residual_true": max(i["rel_residual_true"] for i in infos),
                   "vcycles_timed": tim["vcycles"]},
@@ -412,8 +452,9 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "patch_wave3_kernel (one color of the smoother, finest level)",
-                     "avg_launch_us": per_launch_s * 1e6, "bytes_per_launch": bytes_sweep / 2 ** dim,
+                     "kernel": "patch_wave3_kernel (one color of one batch of the smoother, finest level)",
+                     "avg_launch_us": per_launch_s * 1e6, "bytes_per_launch": bytes_sweep / lps,
+                     "launches_per_sweep": lps,
                      "measured_copy_gbs": copy_gbs},
         "cpu_baseline": cpu,
         "other_workloads": extras,

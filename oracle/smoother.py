@@ -197,6 +197,42 @@ def sweep_alg3(A, b, u, patches: Patches, solvers: LocalSolvers, reverse: bool =
     return u
 
 
+def batch_of(patches: Patches, j: int, batch_layers: int) -> int:
+    """Batch of patch j: its vertex coordinate in the slowest direction, in slabs of batch_layers layers."""
+    return (patches.verts[j][patches.dim - 1] - 1) // batch_layers
+
+
+def batched_order(patches: Patches, batch_layers: int, reverse: bool = False):
+    """The (batch, color) groups of the batch-processing smoother (Algorithm 5, Section 4.1).
+
+    Patches are in lexicographic order (slowest direction last), grouped by
+    color with that order kept, and each color is cut into batches of whole
+    layers of patches along the slowest direction; the outer loop is over
+    batches, the inner one over colors.  The reverse sweep is the whole
+    sequence backwards.
+    """
+    nb = (patches.n_cells - 2) // batch_layers + 1
+    groups = []
+    for bi in range(nb):
+        for c in colors_in_order(patches.dim):
+            groups.append([j for j in patches.by_color[c] if batch_of(patches, j, batch_layers) == bi])
+    return groups[::-1] if reverse else groups
+
+
+def sweep_batched(A, b, u, patches: Patches, solvers: LocalSolvers, batch_layers: int,
+                  reverse: bool = False) -> np.ndarray:
+    """Batch-processing combined colorized smoother (Algorithm 5) in the Algorithm 3 form per group."""
+    u = np.array(u, dtype=np.float64, copy=True)
+    for group in batched_order(patches, batch_layers, reverse):
+        if not group:
+            continue
+        r = b - A @ u
+        for j in group:
+            I = patches.interior[j]
+            u[I] += solvers.apply(j, r[I])
+    return u
+
+
 def sweep_alg1(A, b, u, patches: Patches, solvers: LocalSolvers, reverse: bool = False) -> np.ndarray:
     """Algorithm 1: the global residual recomputed before every patch (tiny meshes)."""
     u = np.array(u, dtype=np.float64, copy=True)

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -362,7 +363,8 @@ vps_dtype vdt(const vps_context* c) { return (vps_dtype)c->cfg.vcycle_dtype; }
 
 hipError_t do_operator(vps_context* c, int l, const void* u, const void* b, void* out, vps_dtype t);
 
-hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dtype t, int color) {
+hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dtype t, int color, int vlo = 0,
+                           int vhi = 0) {
   const Level& L = c->lv[l];
   const int k = c->cfg.degree, d = c->cfg.dim, coef = c->cfg.coef;
   vps::PatchLaunch P{};
@@ -376,6 +378,8 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   P.coef = coef;
   P.pb = c->cfg.patches_per_block;  // 0: the launcher chooses
   P.order = c->cfg.patch_order;
+  P.vlo = vlo;
+  P.vhi = vhi;
   if (coef == VPS_COEF_CONST) {
     P.M[0] = L.Mfull.data();
     P.M[1] = nullptr;
@@ -404,7 +408,21 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
 
 hipError_t do_smooth(vps_context* c, int l, void* u, const void* b, vps_dtype t, int sweeps, bool reverse) {
   const int nc = 1 << c->cfg.dim;
-  if (c->lv[l].ncell < 2) return hipSuccess;
+  const int N = c->lv[l].ncell, B = c->cfg.batch_layers;
+  if (N < 2) return hipSuccess;
+  if (B > 0 && N - 1 > B) {
+    // Algorithm 5: slabs of B vertex layers, all colors of a slab before the next slab
+    const int nb = (N - 2) / B + 1;
+    for (int s = 0; s < sweeps; ++s)
+      for (int i = 0; i < nb; ++i) {
+        const int bi = reverse ? nb - 1 - i : i;
+        for (int j = 0; j < nc; ++j) {
+          hipError_t e = do_smooth_color(c, l, u, b, t, reverse ? nc - 1 - j : j, 1 + bi * B, std::min(N - 1, (bi + 1) * B));
+          if (e != hipSuccess) return e;
+        }
+      }
+    return hipSuccess;
+  }
   for (int s = 0; s < sweeps; ++s)
     for (int i = 0; i < nc; ++i) {
       hipError_t e = do_smooth_color(c, l, u, b, t, reverse ? nc - 1 - i : i);
@@ -658,6 +676,8 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.stream_min_cells < 0) return VPS_E_ARG;
   if (C.algorithm != VPS_ALG_COMBINED && C.algorithm != VPS_ALG_SEPARATED) return VPS_E_ARG;
   if (C.patch_order < 0 || C.patch_order > 3) return VPS_E_ARG;
+  if (C.batch_layers < 0) return VPS_E_ARG;
+  if (C.batch_layers > 0 && C.algorithm != VPS_ALG_COMBINED) return VPS_E_UNSUPPORTED;
   if (C.algorithm == VPS_ALG_SEPARATED && (C.dim != 3 || C.coef != VPS_COEF_CONST || C.degree < 2 || C.degree > 4))
     return VPS_E_UNSUPPORTED;
   // every node index must fit in int on the kernels' inner indexing

@@ -40,6 +40,7 @@ struct PatchLaunch {
   const double* To;    // (K-1) x (K-1)
   const double* lam_int;  // Q eigenvalues in the even/odd mode order (host), or null
   int order;              // vps_config.patch_order (3D one-patch-per-wave kernel)
+  int vlo, vhi;           // vertex range (inclusive) in the slowest direction; vhi = 0: all vertices
 };
 
 template <typename T, int K, int D>

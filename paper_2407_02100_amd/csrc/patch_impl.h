@@ -51,9 +51,13 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
   for (int e = 0; e < 3; ++e) {
     if (e >= D) { a.v0[e] = 1; a.np[e] = 1; continue; }
     const int bit = (L.color >> e) & 1;
-    const int v0 = bit ? 1 : 2;
+    int v0 = bit ? 1 : 2, vlast = N - 1;
+    if (e == D - 1 && L.vhi > 0) {  // one batch: the vertex layers [vlo, vhi] of the slowest direction
+      v0 = L.vlo + (((L.vlo & 1) != bit) ? 1 : 0);
+      vlast = std::min(L.vhi, N - 1);
+    }
     a.v0[e] = v0;
-    a.np[e] = (v0 <= N - 1) ? (N - 1 - v0) / 2 + 1 : 0;
+    a.np[e] = (v0 <= vlast) ? (vlast - v0) / 2 + 1 : 0;
     if (a.np[e] == 0) return hipSuccess;  // no patch of this color
   }
   for (int h = 0; h < 2; ++h)

@@ -38,7 +38,8 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def run(dtype: str, n_cells: int = 128, degree: int = 4, algorithm: str = "combined", order: int = 0):
+def run(dtype: str, n_cells: int = 128, degree: int = 4, algorithm: str = "combined", order: int = 0,
+        batch_layers: int = 0):
     if ROOT not in sys.path:
         sys.path.insert(0, ROOT)
     import torch
@@ -52,7 +53,8 @@ def run(dtype: str, n_cells: int = 128, degree: int = 4, algorithm: str = "combi
     del src, dst
     b = torch.from_numpy(vi.seeded_vector(3, degree, n_cells, 5)).to("cuda", tdt)
     u = torch.from_numpy(vi.seeded_vector(3, degree, n_cells, 105)).to("cuda", tdt)
-    with vps.Context(3, degree, n_cells, 1, vcycle_dtype=dtype, algorithm=algorithm, patch_order=order) as ctx:
+    with vps.Context(3, degree, n_cells, 1, vcycle_dtype=dtype, algorithm=algorithm, patch_order=order,
+                     batch_layers=batch_layers) as ctx:
         ctx.smooth(0, u, b, sweeps=1)
         ctx.sync()
     print("traffic probe done", flush=True)
@@ -74,7 +76,7 @@ SMOOTHER_KERNELS = ("patch_wave3_kernel", "patch_color_kernel", "patch_solve3_ke
 
 
 def summarize(fetch_csv: str, write_csv: str, dtype: str, workload: str = "poisson3d_q4_n128",
-              out_path: str | None = None):
+              out_path: str | None = None, batch_layers: int = 0):
     per = {}
     scales = {}
     for label, path in (("fetch", fetch_csv), ("write", write_csv)):
@@ -97,7 +99,7 @@ def summarize(fetch_csv: str, write_csv: str, dtype: str, workload: str = "poiss
         kernels[key] = {"launches": len(f), "fetch_bytes_per_launch": sum(f) / len(f),
                         "write_bytes_per_launch": sum(w) / len(w)}
     sweep = sum((v["fetch_bytes_per_launch"] + v["write_bytes_per_launch"]) * v["launches"] for v in kernels.values())
-    doc = {"workload": workload, "dtype": dtype, "kernel_source_hash": kernel_source_hash(),
+    doc = {"workload": workload, "dtype": dtype, "batch_layers": batch_layers, "kernel_source_hash": kernel_source_hash(),
            "kernels": kernels, "bytes_per_sweep": sweep, "calibration": scales,
            "note": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE per dispatch, each scaled by the value the "
                    "same counter reads for a plain copy of 512 MiB in the same process"}
@@ -118,13 +120,15 @@ if __name__ == "__main__":
     r.add_argument("--dtype", default="f32")
     r.add_argument("--algorithm", default="combined")
     r.add_argument("--order", type=int, default=0, help="vps_config.patch_order")
+    r.add_argument("--batch-layers", type=int, default=0, help="vps_config.batch_layers")
     s = sub.add_parser("summarize")
     s.add_argument("fetch_csv")
     s.add_argument("write_csv")
     s.add_argument("--dtype", default="f32")
     s.add_argument("--out", default=None)
+    s.add_argument("--batch-layers", type=int, default=0, help="the batch_layers the counters were taken with")
     a = ap.parse_args()
     if a.cmd == "run":
-        run(a.dtype, algorithm=a.algorithm, order=a.order)
+        run(a.dtype, algorithm=a.algorithm, order=a.order, batch_layers=a.batch_layers)
     else:
-        summarize(a.fetch_csv, a.write_csv, a.dtype, out_path=a.out)
+        summarize(a.fetch_csv, a.write_csv, a.dtype, out_path=a.out, batch_layers=a.batch_layers)

@@ -157,3 +157,64 @@ def test_mean_solver_spectrum_bounds():
         ev = sla.eigvals(np.linalg.solve(rho8.mean() * Ab, Aj)).real
         assert ev.min() >= rho8.min() / rho8.mean() * (1 - 1e-12)
         assert ev.max() <= rho8.max() / rho8.mean() * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("dim,k,N,B", [(2, 2, 7, 2), (3, 2, 5, 1), (3, 1, 6, 3)])
+@pytest.mark.parametrize("reverse", [False, True])
+def test_batched_sweep_equals_patch_by_patch(dim, k, N, B, reverse):
+    """Algorithm 5 in the grouped form equals the residual recomputed before every patch in the same order."""
+    A = assemble.assemble(dim, k, N)
+    P = smoother.Patches(dim, k, N)
+    S = smoother.LocalSolvers(A, P, "exact")
+    b = vi.seeded_vector(dim, k, N, 81)
+    u0 = vi.seeded_vector(dim, k, N, 82)
+    want = np.array(u0)
+    for group in smoother.batched_order(P, B, reverse):
+        for j in group:
+            r = b - A @ want
+            I = P.interior[j]
+            want[I] += S.apply(j, r[I])
+    got = smoother.sweep_batched(A, b, u0, P, S, B, reverse)
+    assert np.allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+    # every patch exactly once
+    seen = sorted(j for g in smoother.batched_order(P, B) for j in g)
+    assert seen == list(range(len(P)))
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 6), (3, 2, 4)])
+def test_batched_sweep_one_batch_is_colorized(dim, k, N):
+    """A batch holding every layer is the plain colorized sweep (Algorithm 3/4 order)."""
+    A = assemble.assemble(dim, k, N)
+    P = smoother.Patches(dim, k, N)
+    S = smoother.LocalSolvers(A, P, "exact")
+    b = vi.seeded_vector(dim, k, N, 83)
+    u0 = vi.seeded_vector(dim, k, N, 84)
+    for rev in (False, True):
+        assert np.allclose(smoother.sweep_batched(A, b, u0, P, S, N, rev), smoother.sweep_alg3(A, b, u0, P, S, rev),
+                           rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("B,same", [(2, True), (4, True), (1, False), (3, False)])
+def test_batched_sweep_even_layers_keep_the_colorized_iterate(B, same):
+    """Two patches interact only if their vertices differ by at most 1 in every direction.  With batches of
+    an even number of vertex layers, a batch boundary has an even layer below an odd one, so every
+    interacting pair is visited in the colorized order (colors with even slowest-direction parity first):
+    the iterate is exactly the colorized one.  Odd batch sizes reverse some pairs: a different iterate,
+    each step still an A-orthogonal projection (the energy error decreases)."""
+    dim, k, N = 3, 2, 6
+    A = assemble.assemble(dim, k, N)
+    P = smoother.Patches(dim, k, N)
+    S = smoother.LocalSolvers(A, P, "exact")
+    b = vi.seeded_vector(dim, k, N, 85)
+    u0 = vi.seeded_vector(dim, k, N, 86)
+    free = np.flatnonzero(A.diagonal() != 0)
+    us = np.zeros_like(b)
+    us[free] = spla.spsolve(A[free][:, free].tocsc(), b[free])
+    energy = lambda v: float((us - v) @ (A @ (us - v)))
+    ub = smoother.sweep_batched(A, b, u0, P, S, B)
+    uc = smoother.sweep_alg3(A, b, u0, P, S)
+    if same:
+        assert np.array_equal(ub, uc)
+    else:
+        assert np.abs(ub - uc).max() > 1e-6
+    assert energy(ub) < energy(u0)
