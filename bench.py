@@ -69,8 +69,9 @@ def color_counts(dim: int, k: int, n: int, vlo: int = 1, vhi: int | None = None)
 
 
 def batches(n: int, batch_layers: int):
-    """Vertex ranges [lo, hi] of the batches in the slowest direction (one range: whole colors)."""
-    if batch_layers <= 0 or n - 1 <= batch_layers:
+    """Vertex ranges [lo, hi] of the batches in the slowest direction (one range: whole colors; the library
+    batches only levels with more than 2 batch_layers vertex layers)."""
+    if batch_layers <= 0 or n - 1 <= 2 * batch_layers:
         return [(1, n - 1)]
     return [(1 + i * batch_layers, min(n - 1, (i + 1) * batch_layers)) for i in range((n - 2) // batch_layers + 1)]
 

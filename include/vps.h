@@ -102,12 +102,13 @@ typedef struct {
                             the XCDs; 2 = Morton curve, one slab per XCD; 3 = tiles
                             of 4x4x4 patches, one slab per XCD */
   int batch_layers;      /* batch processing (Algorithm 5, Section 4.1) in vps_smooth and
-                            the V-cycle: 0 = whole colors (Algorithm 4); B > 0 = for each
-                            slab of B vertex layers along the slowest direction, all
-                            colors of its patches in turn (reverse sweeps: the whole
-                            sequence backwards).  Even B visits every pair of interacting
-                            patches in the colorized order, i.e. gives Algorithm 4's
-                            iterate.  Combined algorithm only; must be >= 0 */
+                            the V-cycle: 0 = whole colors (Algorithm 4); B > 0 = on levels
+                            with more than 2B vertex layers per direction, for each slab
+                            of B vertex layers along the slowest direction, all colors of
+                            its patches in turn (reverse sweeps: the whole sequence
+                            backwards); smaller levels sweep whole colors.  Even B visits
+                            every pair of interacting patches in the colorized order, i.e.
+                            gives Algorithm 4's iterate.  Combined algorithm only; >= 0 */
 } vps_config;
 
 typedef struct {

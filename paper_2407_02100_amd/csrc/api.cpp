@@ -410,8 +410,9 @@ hipError_t do_smooth(vps_context* c, int l, void* u, const void* b, vps_dtype t,
   const int nc = 1 << c->cfg.dim;
   const int N = c->lv[l].ncell, B = c->cfg.batch_layers;
   if (N < 2) return hipSuccess;
-  if (B > 0 && N - 1 > B) {
-    // Algorithm 5: slabs of B vertex layers, all colors of a slab before the next slab
+  if (B > 0 && N - 1 > 2 * B) {
+    // Algorithm 5: slabs of B vertex layers, all colors of a slab before the next slab (levels with
+    // more than 2B layers; the smaller ones fit the Infinity Cache whole and sweep whole colors)
     const int nb = (N - 2) / B + 1;
     for (int s = 0; s < sweeps; ++s)
       for (int i = 0; i < nb; ++i) {

@@ -15,7 +15,8 @@ def vps():
     return m
 
 
-@pytest.mark.parametrize("dim,k,N,B", [(3, 2, 7, 1), (3, 2, 7, 3), (3, 4, 6, 3), (2, 2, 9, 3), (3, 3, 5, 1)])
+# sizes with more than 2B vertex layers (smaller levels sweep whole colors)
+@pytest.mark.parametrize("dim,k,N,B", [(3, 2, 7, 1), (3, 2, 8, 3), (3, 4, 8, 3), (2, 2, 9, 3), (3, 3, 5, 1)])
 @pytest.mark.parametrize("reverse", [False, True])
 def test_batched_sweep_odd_layers(vps, dim, k, N, B, reverse):
     """Odd batch sizes change the patch order: compare with the oracle's batched sweep."""
@@ -51,6 +52,21 @@ def test_batched_even_layers_bitwise(vps, dtype, B):
             ctx.smooth(0, u, dev(b, tdt), sweeps=1, reverse=True)
             out.append(host(u))
     assert np.array_equal(out[0], out[1])
+
+
+def test_batched_small_level_sweeps_whole_colors(vps):
+    """A level with at most 2B vertex layers is swept in whole colors (the plain colorized iterate)."""
+    k, N, B = 2, 7, 3
+    say("batched small level")
+    A = assemble.assemble(3, k, N)
+    P = smoother.Patches(3, k, N)
+    S = smoother.LocalSolvers(A, P, "shared")
+    b = vi.seeded_vector(3, k, N, 96)
+    u0 = vi.seeded_vector(3, k, N, 97)
+    with vps.Context(3, k, N, 1, batch_layers=B) as ctx:
+        u = dev(u0)
+        ctx.smooth(0, u, dev(b), sweeps=1)
+        assert rel(host(u), smoother.sweep_alg3(A, b, u0, P, S)) <= 1e-12
 
 
 def test_batched_solve_odd_layers(vps):
