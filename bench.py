@@ -320,8 +320,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build runs the smoother on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the smoother runs on a single MI355X "
+              "(sharding across GPUs is not implemented); use --gpus 1", file=sys.stderr)
         return 2
 
     import vps_inputs as vi
