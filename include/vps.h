@@ -109,6 +109,12 @@ typedef struct {
                             backwards); smaller levels sweep whole colors.  Even B visits
                             every pair of interacting patches in the colorized order, i.e.
                             gives Algorithm 4's iterate.  Combined algorithm only; >= 0 */
+  int patches_per_wave;  /* 3D, rho = 1, degree 2..4, combined algorithm, patch_order 0:
+                            patches of a color per wavefront in the smoother: 1 = one
+                            patch; 2 = two x-adjacent patches that share a closure face
+                            (their boundary columns are loaded together); 0 = automatic
+                            (2, except 1 for FP32 at degree 4).  Same update either
+                            way, different rounding order */
 } vps_config;
 
 typedef struct {

@@ -352,6 +352,13 @@ hipError_t upload(const std::vector<double>& src, void** dst, hipStream_t s) {
 bool level_ok(const vps_context* c, int l) { return c && l >= 0 && l < (int)c->lv.size(); }
 
 // cells per direction from which the plane-streaming kernels are used
+// the two-patches-per-wave smoother kernel: 3D, rho = 1, degree 2..4, combined
+// algorithm, default dispatch order, automatic workgroup shape
+bool pair_kernel_applies(const vps_config& C) {
+  return C.dim == 3 && C.coef == VPS_COEF_CONST && C.degree >= 2 && C.degree <= 4 &&
+         C.algorithm == VPS_ALG_COMBINED && C.patch_order == 0 && C.patches_per_block == 0;
+}
+
 int stream_min(const vps_context* c) {
   if (c->cfg.dim == 3 && c->cfg.degree == 5) return 1;  // the single-pass 3D tiles exceed the LDS at k = 5
   return c->cfg.stream_min_cells > 0 ? c->cfg.stream_min_cells : 32;
@@ -378,6 +385,11 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   P.coef = coef;
   P.pb = c->cfg.patches_per_block;  // 0: the launcher chooses
   P.order = c->cfg.patch_order;
+  // automatic: pairs, except FP32 at degree 4 (there one patch per wave is as fast on
+  // whole colors and faster in slab batches, measured at 513^3)
+  const bool pair_auto = !(t == VPS_F32 && c->cfg.degree == 4);
+  P.ppw = pair_kernel_applies(c->cfg) && (c->cfg.patches_per_wave == 2 || (c->cfg.patches_per_wave == 0 && pair_auto))
+              ? 2 : 1;
   P.vlo = vlo;
   P.vhi = vhi;
   if (coef == VPS_COEF_CONST) {
@@ -679,6 +691,8 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.patch_order < 0 || C.patch_order > 3) return VPS_E_ARG;
   if (C.batch_layers < 0) return VPS_E_ARG;
   if (C.batch_layers > 0 && C.algorithm != VPS_ALG_COMBINED) return VPS_E_UNSUPPORTED;
+  if (C.patches_per_wave < 0 || C.patches_per_wave > 2) return VPS_E_ARG;
+  if (C.patches_per_wave == 2 && !pair_kernel_applies(C)) return VPS_E_UNSUPPORTED;
   if (C.algorithm == VPS_ALG_SEPARATED && (C.dim != 3 || C.coef != VPS_COEF_CONST || C.degree < 2 || C.degree > 4))
     return VPS_E_UNSUPPORTED;
   // every node index must fit in int on the kernels' inner indexing

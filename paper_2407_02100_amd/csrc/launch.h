@@ -40,6 +40,7 @@ struct PatchLaunch {
   const double* To;    // (K-1) x (K-1)
   const double* lam_int;  // Q eigenvalues in the even/odd mode order (host), or null
   int order;              // vps_config.patch_order (3D one-patch-per-wave kernel)
+  int ppw;                // 3D, rho = 1, K = 2..4: patches per wavefront (1 or 2)
   int vlo, vhi;           // vertex range (inclusive) in the slowest direction; vhi = 0: all vertices
 };
 

@@ -4,6 +4,7 @@
 
 #include "kernels.h"
 #include "patch_wave.h"
+#include "patch_pair.h"
 #include "patch_solve.h"
 #include "launch.h"
 
@@ -70,6 +71,38 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
   if (D == 3 && L.coef == 0 && L.pb == 0) {
     if constexpr (K >= 2 && K <= 4) {  // (2K-1)^2 interior lines must fit the 64 lanes of a wave
       static_assert(sizeof(WaveArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
+      static_assert(sizeof(PairArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
+      const unsigned long long vbytes = (unsigned long long)a.n1 * a.n1 * a.n1 * sizeof(T);
+      if (vbytes >= (1ull << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
+      if (L.ppw == 2) {
+        if (L.order != 0) return hipErrorInvalidValue;  // pairs are visited in lexicographic order only
+        PairArgs<T, K> w;
+        w.u = a.u;
+        w.b = a.b;
+        w.n1 = a.n1;
+        for (int e = 0; e < 3; ++e) {
+          w.v0[e] = a.v0[e];
+          w.np[e] = a.np[e];
+        }
+        w.ngx = (a.np[0] + 1) / 2;
+        const unsigned long long ng = (unsigned long long)w.ngx * (unsigned)a.np[1] * (unsigned)a.np[2];
+        // the pair decomposition divides numbers below ngroups by ngx and np[1]
+        if (ng * (unsigned)w.ngx >= (1ull << 32) || ng * (unsigned)a.np[1] >= (1ull << 32)) return hipErrorInvalidValue;
+        w.ngroups = (unsigned)ng;
+        w.vec_bytes = (unsigned)vbytes;
+        w.magic_g = magic_of((unsigned)w.ngx);
+        w.magic_y = magic_of((unsigned)a.np[1]);
+        for (int i = 0; i < Q * P; ++i) {
+          w.M[i] = a.m.M[0][i];
+          w.Kst[i] = a.m.Kst[0][i];
+        }
+        for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
+        for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
+        for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];
+        const unsigned grid = (w.ngroups + kXcd - 1) / kXcd * kXcd;  // a multiple of the XCD count
+        patch_pair3_kernel<T, K><<<grid, 64, 0, s>>>(w);
+        return hipGetLastError();
+      }
       WaveArgs<T, K> w;
       w.u = a.u;
       w.b = a.b;
@@ -83,11 +116,9 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
       if ((unsigned long long)w.npatch * (unsigned)a.np[0] >= (1ull << 32) ||
           (unsigned long long)w.npatch * (unsigned)a.np[1] >= (1ull << 32))
         return hipErrorInvalidValue;
-      const unsigned long long vbytes = (unsigned long long)a.n1 * a.n1 * a.n1 * sizeof(T);
-      if (vbytes >= (1ull << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
       w.vec_bytes = (unsigned)vbytes;
-      w.magic_x = (unsigned)((1ull << 32) / (unsigned)a.np[0] + 1);
-      w.magic_y = (unsigned)((1ull << 32) / (unsigned)a.np[1] + 1);
+      w.magic_x = magic_of((unsigned)a.np[0]);
+      w.magic_y = magic_of((unsigned)a.np[1]);
       for (int i = 0; i < Q * P; ++i) {
         w.M[i] = a.m.M[0][i];
         w.Kst[i] = a.m.Kst[0][i];
@@ -155,8 +186,8 @@ hipError_t launch_patch_solve(const PatchLaunch& L, const void* r, hipStream_t s
     const unsigned long long vbytes = (unsigned long long)L.n1 * L.n1 * L.n1 * sizeof(T);
     if (vbytes >= (1ull << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
     w.vec_bytes = (unsigned)vbytes;
-    w.magic_x = (unsigned)((1ull << 32) / (unsigned)w.np[0] + 1);
-    w.magic_y = (unsigned)((1ull << 32) / (unsigned)w.np[1] + 1);
+    w.magic_x = magic_of((unsigned)w.np[0]);
+    w.magic_y = magic_of((unsigned)w.np[1]);
     for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
     for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
     for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];

@@ -20,7 +20,7 @@ struct SolveArgs {
   int np[3];
   unsigned npatch;
   unsigned vec_bytes;  // bytes of one level vector (< 2^32)
-  unsigned magic_x, magic_y;  // n / d = umulhi(n, floor(2^32 / d) + 1) for d = np[0], np[1]
+  unsigned magic_x, magic_y;  // magic_of(np[0]), magic_of(np[1]) (see div_magic)
   WaveFdm<T, K> f;
   T lam[2 * K - 1];  // 1D generalized eigenvalues in the internal mode order
 };
@@ -51,8 +51,8 @@ __global__ void __launch_bounds__(64) patch_solve3_kernel(const SolveArgs<T, K> 
   if (logical >= a.npatch) return;
   const int lane = threadIdx.x;
   const unsigned npx = (unsigned)a.np[0], npy = (unsigned)a.np[1];
-  const unsigned qx = __umulhi(logical, a.magic_x);
-  const unsigned qy = __umulhi(qx, a.magic_y);
+  const unsigned qx = div_magic(logical, npx, a.magic_x);
+  const unsigned qy = div_magic(qx, npy, a.magic_y);
   const int px = (int)(logical - qx * npx);
   const int py = (int)(qx - qy * npy);
   const int pz = (int)qy;

@@ -108,9 +108,7 @@ struct WaveArgs {
   int np[3];
   unsigned npatch;
   unsigned vec_bytes;  // bytes of one level vector (< 2^32)
-  // exact division by np[0] and np[1] for dividends below 2^32 / divisor:
-  // n / d = umulhi(n, floor(2^32 / d) + 1)
-  unsigned magic_x, magic_y;
+  unsigned magic_x, magic_y;  // magic_of(np[0]), magic_of(np[1]) (see div_magic)
   // order in which the workgroups visit the color's patches (dispatch-order study):
   // 0 lexicographic in one slab per XCD, 1 lexicographic dealt round-robin over the XCDs,
   // 2 Morton curve over a 2^cover_log2 cube in one slab per XCD, 3 tiles of 4^3 patches in one slab per XCD
@@ -131,6 +129,14 @@ __device__ inline void boundary_column(int lane, int& y, int& x) {
   else if (lane < 2 * P) { y = P - 1; x = lane - P; }
   else { const int r = lane - 2 * P; y = 1 + (r >> 1); x = (r & 1) ? P - 1 : 0; }
 }
+
+// n / d for a divisor d of the launch: umulhi(n, floor(2^32 / d) + 1) is exact
+// for n * d < 2^32 and d >= 2; d = 1 (whose multiplier 2^32 + 1 does not fit)
+// is taken apart.
+__device__ inline unsigned div_magic(unsigned n, unsigned d, unsigned magic) {
+  return d == 1u ? n : __umulhi(n, magic);
+}
+__host__ inline unsigned magic_of(unsigned d) { return d >= 2u ? (unsigned)((1ull << 32) / d + 1) : 0u; }
 
 // Raw buffer accesses: a wave-uniform descriptor over a whole level vector,
 // a wave-uniform byte offset (SGPR) and a 32-bit per-lane byte offset.
@@ -181,8 +187,8 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
   const unsigned npx = (unsigned)a.np[0], npy = (unsigned)a.np[1];
   int px, py, pz;
   if (a.order <= 1) {
-    const unsigned qx = __umulhi(logical, a.magic_x);
-    const unsigned qy = __umulhi(qx, a.magic_y);
+    const unsigned qx = div_magic(logical, npx, a.magic_x);
+    const unsigned qy = div_magic(qx, npy, a.magic_y);
     px = (int)(logical - qx * npx);
     py = (int)(qx - qy * npy);
     pz = (int)qy;

@@ -58,12 +58,20 @@ def test_status_strings(lib):
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patch_order=4), -1),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, batch_layers=-1), -1),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, algorithm=1, batch_layers=2), -2),
+    (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=3), -1),
+    (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=-1), -1),
+    (dict(dim=2, degree=2, n_cells=8, n_levels=2, patches_per_wave=2), -2),   # pairs: 3D only
+    (dict(dim=3, degree=1, n_cells=8, n_levels=2, patches_per_wave=2), -2),   # pairs: degree 2..4
+    (dict(dim=3, degree=5, n_cells=8, n_levels=2, patches_per_wave=2), -2),
+    (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=2, patch_order=1), -2),
+    (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=2, algorithm=1), -2),
+    (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=2, patches_per_block=2), -2),
 ])
 def test_create_rejects_invalid_configurations(lib, cfg, status):
     from paper_2407_02100_amd import vps
     c = vps.vps_config(cfg["dim"], cfg["degree"], cfg["n_cells"], cfg["n_levels"], cfg.get("pre", 1), 1, 0, 0,
                        cfg.get("patches_per_block", 0), cfg.get("stream_min_cells", 0), cfg.get("algorithm", 0),
-                       cfg.get("patch_order", 0), cfg.get("batch_layers", 0))
+                       cfg.get("patch_order", 0), cfg.get("batch_layers", 0), cfg.get("patches_per_wave", 0))
     h = ctypes.c_void_p()
     st = vps.lib().vps_create(ctypes.byref(c), None, ctypes.byref(h))
     assert st == status

@@ -1,0 +1,124 @@
+"""GPU parity of the smoother kernel that takes two x-adjacent patches of a color per wavefront.
+
+The pair shares one closure face, so the wavefront loads the union of the two
+closures once; the update is the same exact local solve as with one patch per
+wavefront.  Sizes give colors with an even and an odd number of patches along
+x (a last pair with one patch) and several pairs along y and z.
+"""
+import numpy as np
+import pytest
+
+import vps_inputs as vi
+from oracle import assemble, smoother
+from tests.gpu_util import dev, host, rel, say
+
+pytestmark = pytest.mark.gpu
+
+# (k, N): N - 1 interior vertices per direction; colors have (N - 1) // 2 or N // 2 patches along x
+PAIR_CASES = [(2, 7), (2, 8), (3, 5), (3, 6), (4, 5), (4, 6), (2, 11)]
+
+
+@pytest.fixture(scope="module")
+def vps():
+    from paper_2407_02100_amd import vps as m
+    return m
+
+
+@pytest.mark.parametrize("k,N", PAIR_CASES)
+def test_pair_colors_fp64(vps, k, N):
+    """Every color, FP64, against the oracle's colorized sweep (Algorithm 3 form) color by color."""
+    say("pair colors fp64", k, N)
+    A = assemble.assemble_kron(3, k, N)
+    P = smoother.Patches(3, k, N)
+    S = smoother.LocalSolvers(A, P, "shared")
+    b = vi.seeded_vector(3, k, N, 71)
+    uo = vi.seeded_vector(3, k, N, 72)
+    with vps.Context(3, k, N, 1, patches_per_wave=2) as ctx:
+        u = dev(uo)
+        bd = dev(b)
+        for c in range(8):
+            ctx.smooth_color(0, u, bd, c)
+            uo = smoother.apply_color(A, b, uo, P, S, c)
+            assert rel(host(u), uo) <= 1e-12, (c, rel(host(u), uo))
+
+
+@pytest.mark.parametrize("k,N", [(2, 8), (3, 5), (4, 6)])
+@pytest.mark.parametrize("reverse", [False, True])
+def test_pair_sweep_fp32(vps, k, N, reverse):
+    """FP32 sweeps with pairs: against the oracle (FP32 rounding) and against one patch per wavefront."""
+    import torch
+    say("pair sweep fp32", k, N, reverse)
+    A = assemble.assemble_kron(3, k, N)
+    P = smoother.Patches(3, k, N)
+    S = smoother.LocalSolvers(A, P, "shared")
+    b = vi.seeded_vector(3, k, N, 73).astype(np.float32).astype(np.float64)
+    u0 = vi.seeded_vector(3, k, N, 74).astype(np.float32).astype(np.float64)
+    want = smoother.sweep_alg3(A, b, u0, P, S, reverse=reverse)
+    out = {}
+    for ppw in (1, 2):
+        with vps.Context(3, k, N, 1, vcycle_dtype="f32", patches_per_wave=ppw) as ctx:
+            u = dev(u0, torch.float32)
+            ctx.smooth(0, u, dev(b, torch.float32), sweeps=1, reverse=reverse)
+            out[ppw] = host(u)
+    assert rel(out[2], want) <= 2e-5
+    assert rel(out[2], out[1]) <= 2e-5
+
+
+@pytest.mark.parametrize("dtype,k,auto", [("f32", 4, 1), ("f32", 3, 2), ("f64", 4, 2), ("f64", 2, 2)])
+def test_automatic_patches_per_wave(vps, dtype, k, auto):
+    """patches_per_wave=0 takes pairs except FP32 at degree 4: the same bits as that choice made explicit."""
+    import torch
+    N = 9
+    say("automatic patches per wave", dtype, k)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    b = vi.seeded_vector(3, k, N, 75)
+    u0 = vi.seeded_vector(3, k, N, 76)
+    out = {}
+    for ppw in (0, 1, 2):
+        with vps.Context(3, k, N, 1, vcycle_dtype=dtype, patches_per_wave=ppw) as ctx:
+            u = dev(u0, tdt)
+            ctx.smooth(0, u, dev(b, tdt), sweeps=1)
+            out[ppw] = host(u)
+    assert np.array_equal(out[0], out[auto])
+    assert not np.array_equal(out[1], out[2])  # a different rounding order
+    assert rel(out[1], out[2]) <= (2e-5 if dtype == "f32" else 1e-13)
+
+
+def test_pair_batched_fp64_matches_whole_colors(vps):
+    """Slabs of 2 vertex layers (even: Algorithm 4's iterate) with pairs, FP64."""
+    k, N = 3, 10
+    say("pair batched fp64")
+    b = vi.seeded_vector(3, k, N, 77)
+    u0 = vi.seeded_vector(3, k, N, 78)
+    out = {}
+    for B in (0, 2):
+        with vps.Context(3, k, N, 1, patches_per_wave=2, batch_layers=B) as ctx:
+            u = dev(u0)
+            ctx.smooth(0, u, dev(b), sweeps=1)
+            out[B] = host(u)
+    A = assemble.assemble_kron(3, k, N)
+    P = smoother.Patches(3, k, N)
+    S = smoother.LocalSolvers(A, P, "shared")
+    want = smoother.sweep_alg3(A, b, u0, P, S)
+    assert rel(out[0], want) <= 1e-12
+    assert rel(out[2], want) <= 1e-12
+
+
+@pytest.mark.parametrize("k,N", [(2, 3), (2, 4), (3, 4), (4, 3), (4, 4)])
+@pytest.mark.parametrize("form", ["wave", "pair", "separated"])
+def test_rows_of_one_patch_fp64(vps, k, N, form):
+    """Colors with a single patch (or a single pair) along x or y: the patch decomposition divides by 1."""
+    say("rows of one patch", k, N, form)
+    A = assemble.assemble_kron(3, k, N)
+    P = smoother.Patches(3, k, N)
+    S = smoother.LocalSolvers(A, P, "shared")
+    b = vi.seeded_vector(3, k, N, 79)
+    uo = vi.seeded_vector(3, k, N, 80)
+    kw = dict(wave=dict(patches_per_wave=1), pair=dict(patches_per_wave=2), separated=dict(algorithm="separated"))[form]
+    with vps.Context(3, k, N, 1, **kw) as ctx:
+        u = dev(uo)
+        bd = dev(b)
+        for c in range(8):
+            ctx.smooth_color(0, u, bd, c)
+            uo = smoother.apply_color(A, b, uo, P, S, c)
+            assert rel(host(u), uo) <= 1e-12, (c, rel(host(u), uo))

@@ -143,14 +143,14 @@ def test_coarse_solve(vps, dim, k, N0):
 
 @pytest.mark.parametrize("k,N", [(4, 20), (3, 9), (2, 13)])
 def test_patch_order_bitwise(vps, k, N):
-    """The patches of one color are independent: every visiting order gives the same bits."""
+    """The patches of one color are independent: every visiting order gives the same bits (one patch per wave)."""
     import torch
     say("patch order", k, N)
     b = vi.seeded_vector(3, k, N, 61)
     u0 = vi.seeded_vector(3, k, N, 62)
     out = []
     for order in range(4):
-        with vps.Context(3, k, N, 1, patch_order=order) as ctx:
+        with vps.Context(3, k, N, 1, patch_order=order, patches_per_wave=1) as ctx:
             u = dev(u0)
             ctx.smooth(0, u, dev(b), sweeps=1)
             out.append(host(u))
