@@ -132,7 +132,9 @@ typedef struct {
  * allocates the V-cycle work vectors of every level in cfg->vcycle_dtype.
  * hip_stream: a hipStream_t (may be NULL for the null stream).
  * Returns VPS_E_UNSUPPORTED for degree outside 1..5, dim outside {2,3},
- * N not divisible by 2^(n_levels-1) or a coarsest level below 2 cells.
+ * N not divisible by 2^(n_levels-1), a coarsest level below 2 cells, more
+ * than 2e9 nodes, or (3D, rho = 1, degree 2..4) a finest level whose vector in
+ * the V-cycle dtype reaches 4 GiB (the patch kernels use 32-bit byte offsets).
  * A context whose coarsest grid is too large for the coarse solver (rho = 1:
  * more than 15 free nodes per direction in 3D, 63 in 2D; cell coefficient:
  * more than 4096 free nodes) is still created: its smoother, operator and

@@ -698,6 +698,11 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   // every node index must fit in int on the kernels' inner indexing
   const double nodes = std::pow((double)(C.degree * C.n_cells + 1), C.dim);
   if (nodes > 2.0e9) return VPS_E_UNSUPPORTED;
+  // the 3D constant-coefficient patch kernels (degree 2..4) address a level vector of the
+  // V-cycle dtype with 32-bit byte offsets
+  const double vbytes = nodes * (C.vcycle_dtype == VPS_F64 ? 8.0 : 4.0);
+  if (C.dim == 3 && C.coef == VPS_COEF_CONST && C.degree >= 2 && C.degree <= 4 && vbytes >= 4294967296.0)
+    return VPS_E_UNSUPPORTED;
 
   vps_context* c = new vps_context();
   c->cfg = C;

@@ -58,6 +58,7 @@ def test_status_strings(lib):
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patch_order=4), -1),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, batch_layers=-1), -1),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, algorithm=1, batch_layers=2), -2),
+    (dict(dim=3, degree=4, n_cells=204, n_levels=2), -2),  # 817^3 FP64 values exceed 32-bit byte offsets
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=3), -1),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=-1), -1),
     (dict(dim=2, degree=2, n_cells=8, n_levels=2, patches_per_wave=2), -2),   # pairs: 3D only

@@ -122,3 +122,24 @@ def test_rows_of_one_patch_fp64(vps, k, N, form):
             ctx.smooth_color(0, u, bd, c)
             uo = smoother.apply_color(A, b, uo, P, S, c)
             assert rel(host(u), uo) <= 1e-12, (c, rel(host(u), uo))
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("form", ["wave", "pair", "separated"])
+def test_single_patch_domain_fp64(vps, k, form):
+    """N = 2: one patch covers the domain, so one sweep is the exact solve (b - A u = 0 afterwards)."""
+    say("single patch domain", k, form)
+    N = 2
+    A = assemble.assemble_kron(3, k, N)
+    P = smoother.Patches(3, k, N)
+    S = smoother.LocalSolvers(A, P, "shared")
+    b = vi.seeded_vector(3, k, N, 81)
+    u0 = vi.seeded_vector(3, k, N, 82)
+    want = smoother.sweep_alg3(A, b, u0, P, S)
+    kw = dict(wave=dict(patches_per_wave=1), pair=dict(patches_per_wave=2), separated=dict(algorithm="separated"))[form]
+    with vps.Context(3, k, N, 1, **kw) as ctx:
+        u = dev(u0)
+        ctx.smooth(0, u, dev(b), sweeps=1)
+        got = host(u)
+    assert rel(got, want) <= 1e-12
+    assert np.abs(b - A @ got).max() <= 1e-10 * np.abs(b).max()
