@@ -65,18 +65,19 @@ def _sample_vertices(n_cells, color, count, seed):
 
 
 @pytest.mark.parametrize("dtype,color", [("f32", 0), ("f32", 5), ("f64", 3)])
-def test_color_on_sampled_patches_full_size(vps, dtype, color):
-    """One color launch at 513^3 against the oracle's exact local solve of sampled patches."""
+@pytest.mark.parametrize("ppw", [1, 2])
+def test_color_on_sampled_patches_full_size(vps, dtype, color, ppw):
+    """One color launch at 513^3 against the oracle's exact local solve of sampled patches (1 or 2 patches per wave)."""
     import torch
     k, N = K5, N5
-    say("full-size color", dtype, color)
+    say("full-size color", dtype, color, ppw)
     tdt = torch.float32 if dtype == "f32" else torch.float64
     u0 = vi.seeded_vector(3, k, N, 105)
     b = vi.seeded_vector(3, k, N, 5)
     if dtype == "f32":  # the oracle sees the values the kernel sees
         u0 = u0.astype(np.float32).astype(np.float64)
         b = b.astype(np.float32).astype(np.float64)
-    with vps.Context(3, k, N, 1, vcycle_dtype=dtype) as ctx:
+    with vps.Context(3, k, N, 1, vcycle_dtype=dtype, patches_per_wave=ppw) as ctx:
         u = dev(u0, tdt)
         ctx.smooth_color(0, u, dev(b, tdt), color)
         u1 = host(u)
