@@ -92,10 +92,7 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
         w.vec_bytes = (unsigned)vbytes;
         w.magic_g = magic_of((unsigned)w.ngx);
         w.magic_y = magic_of((unsigned)a.np[1]);
-        for (int i = 0; i < Q * P; ++i) {
-          w.M[i] = a.m.M[0][i];
-          w.Kst[i] = a.m.Kst[0][i];
-        }
+        if (!make_band<T, K>(L.M[0], L.Kst[0], &w.band)) return hipErrorInvalidValue;
         for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
         for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
         for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];
@@ -119,10 +116,7 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
       w.vec_bytes = (unsigned)vbytes;
       w.magic_x = magic_of((unsigned)a.np[0]);
       w.magic_y = magic_of((unsigned)a.np[1]);
-      for (int i = 0; i < Q * P; ++i) {
-        w.M[i] = a.m.M[0][i];
-        w.Kst[i] = a.m.Kst[0][i];
-      }
+      if (!make_band<T, K>(L.M[0], L.Kst[0], &w.band)) return hipErrorInvalidValue;
       for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
       for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
       for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];

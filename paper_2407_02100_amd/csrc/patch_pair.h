@@ -45,8 +45,7 @@ struct PairArgs {
   unsigned ngroups;    // ngx * np[1] * np[2]
   unsigned vec_bytes;  // bytes of one level vector (< 2^32)
   unsigned magic_g, magic_y;  // magic_of(ngx), magic_of(np[1]) (see div_magic)
-  T M[(2 * K - 1) * (2 * K + 1)];    // interior rows of the 2-cell patch mass matrix
-  T Kst[(2 * K - 1) * (2 * K + 1)];  // ... and stiffness matrix
+  PatchBand<T, K> band;  // interior rows of the 2-cell patch mass and stiffness matrices
   WaveFdm<T, K> f;
   T lam[2 * K - 1];  // 1D generalized eigenvalues in the internal mode order
 };
@@ -135,8 +134,8 @@ __global__ void __launch_bounds__(64) patch_pair3_kernel(const PairArgs<T, K> a)
 #pragma unroll
         for (int z = 0; z < P; ++z) {
           if (z < band_lo(j, K) || z > band_hi(j, K)) continue;
-          zm = fma(a.M[o * P + z], vb[z], zm);
-          zk = fma(a.Kst[o * P + z], vb[z], zk);
+          zm = fma(band_m(a.band, j, z), vb[z], zm);
+          zk = fma(band_k(a.band, j, z), vb[z], zk);
         }
         Z[(0 * Q + o) * P2 + by * P + bx - x0] = zm;
         Z[(1 * Q + o) * P2 + by * P + bx - x0] = zk;
@@ -148,8 +147,8 @@ __global__ void __launch_bounds__(64) patch_pair3_kernel(const PairArgs<T, K> a)
       for (int o = 0; o < Q; ++o) {
         const int j = o + 1;
         T zm = T(0), zk = T(0);
-        if (band_lo(j, K) == 0) { zm = fma(a.M[o * P], e0[p], zm); zk = fma(a.Kst[o * P], e0[p], zk); }
-        if (band_hi(j, K) == P - 1) { zm = fma(a.M[o * P + P - 1], e1[p], zm); zk = fma(a.Kst[o * P + P - 1], e1[p], zk); }
+        if (band_lo(j, K) == 0) { zm = fma(band_m(a.band, j, 0), e0[p], zm); zk = fma(band_k(a.band, j, 0), e0[p], zk); }
+        if (band_hi(j, K) == P - 1) { zm = fma(band_m(a.band, j, P - 1), e1[p], zm); zk = fma(band_k(a.band, j, P - 1), e1[p], zk); }
         Z[(0 * Q + o) * P2 + col] = zm;
         Z[(1 * Q + o) * P2 + col] = zk;
       }
@@ -172,9 +171,9 @@ __global__ void __launch_bounds__(64) patch_pair3_kernel(const PairArgs<T, K> a)
 #pragma unroll
         for (int x = 0; x < P; ++x) {
           if (x < band_lo(j, K) || x > band_hi(j, K)) continue;
-          av = fma(a.M[o * P + x], zm[x], av);
-          ev = fma(a.Kst[o * P + x], zm[x], ev);
-          ev = fma(a.M[o * P + x], zk[x], ev);
+          av = fma(band_m(a.band, j, x), zm[x], av);
+          ev = fma(band_k(a.band, j, x), zm[x], ev);
+          ev = fma(band_m(a.band, j, x), zk[x], ev);
         }
         AE[((0 * Q + oz) * P + y) * Q + o] = av;
         AE[((1 * Q + oz) * P + y) * Q + o] = ev;
@@ -199,8 +198,8 @@ __global__ void __launch_bounds__(64) patch_pair3_kernel(const PairArgs<T, K> a)
 #pragma unroll
         for (int y = 0; y < P; ++y) {
           if (y < band_lo(j, K) || y > band_hi(j, K)) continue;
-          acc = fma(a.Kst[o * P + y], av[y], acc);
-          acc = fma(a.M[o * P + y], ev[y], acc);
+          acc = fma(band_k(a.band, j, y), av[y], acc);
+          acc = fma(band_m(a.band, j, y), ev[y], acc);
         }
         r[o] = bv[p][o] - acc;
       }

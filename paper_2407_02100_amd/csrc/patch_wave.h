@@ -47,6 +47,55 @@ struct WaveFdm {
   T To[(K - 1) * (K - 1)];  // To[i*(K-1) + j]: component i (0..K-2) of antisymmetric mode j
 };
 
+// The interior rows of the 2-cell patch mass and stiffness matrices (the
+// residual's 1D factors), held as one cell's matrices: a uniform mesh repeats
+// the cell matrix, so the (2K-1) x (2K+1) band has (K+1)^2 distinct entries
+// per matrix, and unrolled loops address them at compile time.
+template <typename T, int K>
+struct PatchBand {
+  T m[(K + 1) * (K + 1)];  // cell mass matrix, row-major (entry [K][K] unused)
+  T k[(K + 1) * (K + 1)];  // cell stiffness matrix
+  T mvv, kvv;              // the middle vertex's diagonal: the sum over both cells
+};
+
+// entry (j, z) of the band, interior node j in 1..2K-1, closure node z in j's cells
+template <typename T, int K>
+__device__ inline T band_at(const T (&c)[(K + 1) * (K + 1)], T vv, int j, int z) {
+  constexpr int W = K + 1;
+  if (j < K) return c[j * W + z];            // first cell
+  if (j > K) return c[(j - K) * W + z - K];  // second cell
+  if (z < K) return c[K * W + z];            // middle vertex, first cell
+  if (z > K) return c[z - K];                // middle vertex, second cell (its row 0)
+  return vv;
+}
+template <typename T, int K>
+__device__ inline T band_m(const PatchBand<T, K>& b, int j, int z) { return band_at<T, K>(b.m, b.mvv, j, z); }
+template <typename T, int K>
+__device__ inline T band_k(const PatchBand<T, K>& b, int j, int z) { return band_at<T, K>(b.k, b.kvv, j, z); }
+
+// Fill a PatchBand from the interior rows (Q x P, row-major) of the 2-cell
+// patch matrices; false if they are not two copies of one cell matrix.
+template <typename T, int K>
+inline bool make_band(const double* Mrows, const double* Krows, PatchBand<T, K>* b) {
+  constexpr int P = 2 * K + 1, W = K + 1;
+  const double* src[2] = {Mrows, Krows};
+  T* dst[2] = {b->m, b->k};
+  for (int t = 0; t < 2; ++t) {
+    const double* R = src[t];
+    T* c = dst[t];
+    for (int i = 0; i < W * W; ++i) c[i] = T(0);
+    for (int a = 1; a <= K; ++a)
+      for (int z = 0; z <= K; ++z)
+        if (!(a == K && z == K)) c[a * W + z] = (T)R[(a - 1) * P + z];
+    for (int z = 1; z <= K; ++z) c[z] = (T)R[(K - 1) * P + K + z];
+    (t == 0 ? b->mvv : b->kvv) = (T)R[(K - 1) * P + K];
+    for (int j = K + 1; j < 2 * K; ++j)
+      for (int z = K; z <= 2 * K; ++z)
+        if ((T)R[(j - 1) * P + z] != c[(j - K) * W + z - K]) return false;
+  }
+  return true;
+}
+
 template <typename T, int K>
 __device__ inline void fdm_forward(const WaveFdm<T, K>& f, const T (&v)[2 * K - 1], T (&out)[2 * K - 1]) {
   constexpr int Q = 2 * K - 1, M = K - 1;  // M = index of the middle node
@@ -116,8 +165,7 @@ struct WaveArgs {
   int cover_log2;
   unsigned nslots;  // workgroups of the launch that map to a position (before the range check)
   int tiles_x, tiles_y;
-  T M[(2 * K - 1) * (2 * K + 1)];    // interior rows of the 2-cell patch mass matrix
-  T Kst[(2 * K - 1) * (2 * K + 1)];  // ... and stiffness matrix
+  PatchBand<T, K> band;  // interior rows of the 2-cell patch mass and stiffness matrices
   WaveFdm<T, K> f;
   T lam[2 * K - 1];  // 1D generalized eigenvalues in the internal mode order
 };
@@ -248,8 +296,8 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
 #pragma unroll
       for (int z = 0; z < P; ++z) {
         if (z < band_lo(j, K) || z > band_hi(j, K)) continue;
-        zm = fma(a.M[o * P + z], vb[z], zm);
-        zk = fma(a.Kst[o * P + z], vb[z], zk);
+        zm = fma(band_m(a.band, j, z), vb[z], zm);
+        zk = fma(band_k(a.band, j, z), vb[z], zk);
       }
       Z[(0 * Q + o) * P2 + by * P + bx] = zm;
       Z[(1 * Q + o) * P2 + by * P + bx] = zk;
@@ -262,8 +310,8 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
     for (int o = 0; o < Q; ++o) {
       const int j = o + 1;
       T zm = T(0), zk = T(0);
-      if (band_lo(j, K) == 0) { zm = fma(a.M[o * P], v0, zm); zk = fma(a.Kst[o * P], v0, zk); }
-      if (band_hi(j, K) == P - 1) { zm = fma(a.M[o * P + P - 1], v1, zm); zk = fma(a.Kst[o * P + P - 1], v1, zk); }
+      if (band_lo(j, K) == 0) { zm = fma(band_m(a.band, j, 0), v0, zm); zk = fma(band_k(a.band, j, 0), v0, zk); }
+      if (band_hi(j, K) == P - 1) { zm = fma(band_m(a.band, j, P - 1), v1, zm); zk = fma(band_k(a.band, j, P - 1), v1, zk); }
       Z[(0 * Q + o) * P2 + iy * P + ix] = zm;
       Z[(1 * Q + o) * P2 + iy * P + ix] = zk;
     }
@@ -286,9 +334,9 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
 #pragma unroll
       for (int y = 0; y < P; ++y) {
         if (y < band_lo(j, K) || y > band_hi(j, K)) continue;
-        av = fma(a.M[o * P + y], zm[y], av);
-        ev = fma(a.Kst[o * P + y], zm[y], ev);
-        ev = fma(a.M[o * P + y], zk[y], ev);
+        av = fma(band_m(a.band, j, y), zm[y], av);
+        ev = fma(band_k(a.band, j, y), zm[y], ev);
+        ev = fma(band_m(a.band, j, y), zk[y], ev);
       }
       AE[((0 * Q + oz) * Q + o) * P + x] = av;
       AE[((1 * Q + oz) * Q + o) * P + x] = ev;
@@ -313,8 +361,8 @@ __global__ void __launch_bounds__(64) patch_wave3_kernel(const WaveArgs<T, K> a)
 #pragma unroll
       for (int x = 0; x < P; ++x) {
         if (x < band_lo(j, K) || x > band_hi(j, K)) continue;
-        s = fma(a.Kst[o * P + x], av[x], s);
-        s = fma(a.M[o * P + x], ev[x], s);
+        s = fma(band_k(a.band, j, x), av[x], s);
+        s = fma(band_m(a.band, j, x), ev[x], s);
       }
       r[o] = B[oz * Q2 + oy * Q + o] - s;
     }
