@@ -294,6 +294,7 @@ def run_extras(torch, vps, vi):
         res[tag] = {"targets_and_dataset_s": t1 - t0, "train_s": hist["seconds"], "train_samples": hist["train_samples"],
                     "val_loss_plain": learned.baseline_loss(T[: hist["val_samples"]]),
                     "val_loss_learned": hist["val_loss"][-1], "plain": cmp["mean"], "learned": cmp["learned"],
+                    "exact_targets": cmp["exact"],
                     "speedup_learned_vs_plain": (cmp["mean"]["seconds"] / cmp["learned"]["seconds"]
                                                  if cmp["mean"]["status"] == 0 else None)}
     out["varcoef3d_q2_n64"] = res

@@ -150,18 +150,45 @@ def convergence_factor(hist, first: int = 3, last: int = 12):
     return (hist[last] / hist[first - 1]) ** (1.0 / (last - first + 1))
 
 
+def apply_exact_targets(ctx):
+    """Set every smoothed level's scaling to the exact training targets clamp(c*, 1/4, 4) of its patches
+    (what a perfect network would output); returns the non-finite counts per level (set to 1)."""
+    import torch
+    bad = []
+    for l in range(1, ctx.n_levels):
+        n = ctx.level_patches(l)
+        r8 = torch.empty((n, 8), dtype=torch.float64, device="cuda")
+        ctx.patch_rho8(l, r8)
+        C = torch.empty((n, 27), dtype=torch.float64, device="cuda")
+        T = torch.empty((n, 27), dtype=torch.float32, device="cuda")
+        ctx.patch_targets(r8, C, T)
+        c = torch.exp(T)
+        ok = torch.isfinite(c)
+        bad.append(int((~ok).sum().item()))
+        c = torch.where(ok, c, torch.ones_like(c)).contiguous()
+        ctx.set_patch_scaling(l, c)
+    ctx.sync()
+    return bad
+
+
 def compare(params, n_cells: int = 64, levels: int = 5, rho_seed: int = 4, rhs_seed: int = 4, rtol: float = 1e-10,
-            maxit: int = 300, corr_len: float = 1.0 / 8.0, iters: int = 12):
-    """Plain rhobar-FDM vs learned scaling on one field: convergence factor and time to rtol."""
+            maxit: int = 300, corr_len: float = 1.0 / 8.0, iters: int = 12, exact: bool = True):
+    """Plain rhobar-FDM vs learned scaling (and, with exact=True, the exact targets the network is
+    trained on) on one field: convergence factor and time to rtol."""
     import torch
     import vps_inputs as vi
     rho = torch.from_numpy(vi.rho_cells(n_cells, rho_seed, corr_len=corr_len)).to("cuda")
     b = torch.from_numpy(vi.seeded_vector(3, 2, n_cells, rhs_seed)).to("cuda")
     out = {}
-    for mode in ("mean", "learned"):
-        with vps.Context(3, 2, n_cells, levels, coef=mode) as ctx:
+    for mode in ("mean", "learned") + (("exact",) if exact else ()):
+        with vps.Context(3, 2, n_cells, levels, coef="learned" if mode == "exact" else mode) as ctx:
             ctx.set_coefficient(rho)
-            fb = apply_scaling(ctx, params) if mode == "learned" else None
+            if mode == "learned":
+                fb = apply_scaling(ctx, params)
+            elif mode == "exact":
+                fb = apply_exact_targets(ctx)
+            else:
+                fb = None
             u = torch.zeros_like(b)
             hist = ctx.vcycle_iterate(b, u, iters)
             x = torch.empty_like(b)

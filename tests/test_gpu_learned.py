@@ -180,3 +180,8 @@ def test_learned_scaling_gain_on_held_out_rough_field(vps):
     assert lrn["status"] == 0 and lrn["rel_residual_true"] <= 1e-10
     assert lrn["factor"] < 0.9 < plain["factor"]
     assert lrn["iterations"] <= plain["iterations"]
+    # the exact targets the network learns (a perfect network) give a contractive V-cycle too
+    ex = res["exact"]
+    say("exact targets", ex["factor"], ex["iterations"])
+    assert all(f == 0 for f in ex["fallback_per_level"])
+    assert ex["status"] == 0 and ex["factor"] < 0.9
