@@ -115,6 +115,12 @@ typedef struct {
                             (their boundary columns are loaded together); 0 = automatic
                             (2, except 1 for FP32 at degree 4).  Same update either
                             way, different rounding order */
+  int vcycle_graph;      /* 1: the finest-level V-cycle of vps_vcycle and vps_solve is
+                            captured once per (input, output) buffer pair into a HIP
+                            graph on a stream of the library's own and replayed on the
+                            context stream (kernel by kernel while the phase timer
+                            runs); 0 (default): launched kernel by kernel.  Same
+                            kernels, same results */
 } vps_config;
 
 typedef struct {

@@ -93,6 +93,15 @@ struct vps_context {
   // MLP work
   vps::MlpWork mlp;
   PhaseTimer timer;
+  // V-cycles captured as HIP graphs, one per (finest-level input, output) pair
+  struct VcycleGraph {
+    const void* b;
+    void* u;
+    hipGraphExec_t exec;
+  };
+  std::vector<VcycleGraph> graphs;
+  hipStream_t capture_stream = nullptr;  // created on the first capture
+  bool graphs_failed = false;            // a capture failed: launch kernel by kernel from then on
 };
 
 namespace {
@@ -559,16 +568,62 @@ hipError_t vcycle_level(vps_context* c, int l, const void* b, void* u) {
   return e;
 }
 
+void drop_graphs(vps_context* c) {
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
+// The finest-level V-cycle from b into u.  With vps_config.vcycle_graph, once
+// per (b, u) pair its launches are captured on a private stream into a HIP
+// graph, which later calls replay on the context stream: one launch instead
+// of a few hundred.  Kernel by kernel otherwise, while the phase timer runs
+// (its events sit between the launches), or after a failed capture.
+hipError_t finest_vcycle(vps_context* c, const void* b, void* u) {
+  const int L = (int)c->lv.size() - 1;
+  if (!c->cfg.vcycle_graph || c->timer.on || c->graphs_failed) return vcycle_level(c, L, b, u);
+  for (const auto& g : c->graphs)
+    if (g.b == b && g.u == u) return hipGraphLaunch(g.exec, c->stream);
+  hipError_t e = hipSuccess;
+  if (!c->capture_stream && (e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
+    c->graphs_failed = true;
+    return vcycle_level(c, L, b, u);
+  }
+  const hipStream_t user = c->stream;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    c->stream = c->capture_stream;
+    const hipError_t ev = vcycle_level(c, L, b, u);
+    c->stream = user;
+    e = hipStreamEndCapture(c->capture_stream, &graph);
+    if (ev != hipSuccess) e = ev;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    c->graphs_failed = true;
+    (void)hipGetLastError();
+    return vcycle_level(c, L, b, u);
+  }
+  if (c->graphs.size() >= 4) {  // keep a few: the solvers use one or two pairs
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.push_back({b, u, exec});
+  return hipGraphLaunch(exec, c->stream);
+}
+
 hipError_t do_vcycle(vps_context* c, const double* r, double* z) {
   const int L = (int)c->lv.size() - 1;
   if (c->timer.on) c->timer.tot.vcycles += 1;
-  if (vdt(c) == VPS_F64) return vcycle_level(c, L, r, z);
+  if (vdt(c) == VPS_F64) return finest_vcycle(c, r, z);
   Level& F = c->lv[L];
   int ti = tbegin(c, PH_CG_VEC, L);
   hipError_t e = vps::launch_cast<double, float>(r, F.b, F.nodes, c->stream);
   if (e != hipSuccess) return e;
   tend(c, ti);
-  if ((e = vcycle_level(c, L, F.b, F.u)) != hipSuccess) return e;
+  if ((e = finest_vcycle(c, F.b, F.u)) != hipSuccess) return e;
   ti = tbegin(c, PH_CG_VEC, L);
   e = vps::launch_cast<float, double>(F.u, z, F.nodes, c->stream);
   tend(c, ti);
@@ -607,7 +662,7 @@ vps_status dots(vps_context* c, const double* x, const double* y, const double* 
 hipError_t vcycle_f32_resident(vps_context* c) {
   const int L = (int)c->lv.size() - 1;
   if (c->timer.on) c->timer.tot.vcycles += 1;
-  return vcycle_level(c, L, c->lv[L].b, c->lv[L].u);
+  return finest_vcycle(c, c->lv[L].b, c->lv[L].u);
 }
 
 vps_status dots_z32(vps_context* c, const double* r, const float* z, const double* q, size_t n, double* out) {
@@ -632,6 +687,9 @@ vps_status ensure_cg(vps_context* c) {
 }
 
 void free_all(vps_context* c) {
+  drop_graphs(c);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+  c->capture_stream = nullptr;
   for (Level& L : c->lv) {
     hipFree(L.u);
     hipFree(L.b);
@@ -693,6 +751,7 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.batch_layers > 0 && C.algorithm != VPS_ALG_COMBINED) return VPS_E_UNSUPPORTED;
   if (C.patches_per_wave < 0 || C.patches_per_wave > 2) return VPS_E_ARG;
   if (C.patches_per_wave == 2 && !pair_kernel_applies(C)) return VPS_E_UNSUPPORTED;
+  if (C.vcycle_graph != 0 && C.vcycle_graph != 1) return VPS_E_ARG;
   if (C.algorithm == VPS_ALG_SEPARATED && (C.dim != 3 || C.coef != VPS_COEF_CONST || C.degree < 2 || C.degree > 4))
     return VPS_E_UNSUPPORTED;
   // every node index must fit in int on the kernels' inner indexing
@@ -801,6 +860,7 @@ long long vps_level_patches(const vps_context* ctx, int level) {
 vps_status vps_set_coefficient(vps_context* c, const double* rho) {
   if (!c || !rho) return fail(c, VPS_E_ARG, "null argument");
   if (c->cfg.coef == VPS_COEF_CONST) return fail(c, VPS_E_STATE, "context was created with coef = VPS_COEF_CONST");
+  drop_graphs(c);  // the coarse solver's buffers may be replaced
   const int d = c->cfg.dim, k = c->cfg.degree;
   const int L = (int)c->lv.size() - 1;
   auto cells = [&](int l) {
@@ -897,6 +957,7 @@ vps_status vps_set_patch_scaling(vps_context* c, int level, const float* cdev) {
   if (!c) return VPS_E_ARG;
   if (!level_ok(c, level)) return fail(c, VPS_E_ARG, "invalid level");
   if (c->cfg.coef != VPS_COEF_CELL_LEARNED) return fail(c, VPS_E_STATE, "context was not created with learned scaling");
+  drop_graphs(c);
   Level& L = c->lv[level];
   const size_t n = (size_t)L.npatch * ipow(2 * c->cfg.degree - 1, c->cfg.dim);
   if (n == 0) return VPS_OK;

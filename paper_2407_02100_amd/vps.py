@@ -37,7 +37,8 @@ class vps_config(ctypes.Structure):
                 ("n_levels", ctypes.c_int), ("pre_sweeps", ctypes.c_int), ("post_sweeps", ctypes.c_int),
                 ("vcycle_dtype", ctypes.c_int), ("coef", ctypes.c_int), ("patches_per_block", ctypes.c_int),
                 ("stream_min_cells", ctypes.c_int), ("algorithm", ctypes.c_int), ("patch_order", ctypes.c_int),
-                ("batch_layers", ctypes.c_int), ("patches_per_wave", ctypes.c_int)]
+                ("batch_layers", ctypes.c_int), ("patches_per_wave", ctypes.c_int),
+                ("vcycle_graph", ctypes.c_int)]
 
 
 class vps_solve_info(ctypes.Structure):
@@ -161,10 +162,10 @@ class Context:
 
     def __init__(self, dim, degree, n_cells, n_levels, pre=1, post=1, vcycle_dtype="f64",
                  coef="const", patches_per_block=0, stream=None, stream_min_cells=0, algorithm="combined",
-                 patch_order=0, batch_layers=0, patches_per_wave=0):
+                 patch_order=0, batch_layers=0, patches_per_wave=0, vcycle_graph=False):
         cfg = vps_config(dim, degree, n_cells, n_levels, pre, post, _DTYPE[vcycle_dtype], _COEF[coef],
                          patches_per_block, stream_min_cells, _ALGORITHM[algorithm], patch_order, batch_layers,
-                         patches_per_wave)
+                         patches_per_wave, int(bool(vcycle_graph)))
         self.cfg = cfg
         self.dim, self.degree, self.n_levels = dim, degree, n_levels
         h = _vp()
