@@ -155,51 +155,59 @@ struct CoarseArgs {
 };
 
 // one line transform along direction `dir` of an n0^D box: out = op(in)
-// transpose=true: out[m] = sum_i T[i][m] in[i]; else out[i] = sum_m T[i][m] in[m]
+// transpose=true: out[m] = sum_i T[i][m] in[i]; else out[i] = sum_m T[i][m] in[m].
+// A work item computes one output of one line (the items of a line share
+// their reads of `in`); Tm is in LDS in 3D.
+constexpr int kCoarseBlock = 1024;
+
 template <typename T, int D>
-__device__ void coarse_lines(const CoarseArgs<T, D>& a, const T* in, T* out, int dir, bool transpose) {
-  const int n = a.n0;
+__device__ void coarse_lines(const T* Tm, int n, const T* in, T* out, int dir, bool transpose) {
   const int nlines = (D == 3) ? n * n : n;
   const int stride = (dir == 0) ? 1 : (dir == 1 ? n : n * n);
-  for (int w = threadIdx.x; w < nlines; w += kBlock) {
+  for (int w = threadIdx.x; w < nlines * n; w += kCoarseBlock) {
+    const int line = w / n, o = w % n;
     int base;
-    if (dir == 0) base = w * n;
-    else if (dir == 1) base = (D == 3) ? (w / n) * n * n + (w % n) : w;
-    else base = w;
-    for (int o = 0; o < n; ++o) {
-      T s = T(0);
-      for (int i = 0; i < n; ++i) s += (transpose ? a.T0[i * n + o] : a.T0[o * n + i]) * in[base + i * stride];
-      out[base + o * stride] = s;
-    }
+    if (dir == 0) base = line * n;
+    else if (dir == 1) base = (D == 3) ? (line / n) * n * n + (line % n) : line;
+    else base = line;
+    T s = T(0);
+    for (int i = 0; i < n; ++i) s += (transpose ? Tm[i * n + o] : Tm[o * n + i]) * in[base + i * stride];
+    out[base + o * stride] = s;
   }
 }
 
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) coarse_fdm_kernel(const CoarseArgs<T, D> a) {
+__global__ void __launch_bounds__(kCoarseBlock) coarse_fdm_kernel(const CoarseArgs<T, D> a) {
   constexpr int NMAX = CoarseArgs<T, D>::NMAX;
   constexpr int SZ = (D == 3) ? NMAX * NMAX * NMAX : NMAX * NMAX;
   __shared__ T A[SZ];
   __shared__ T B[SZ];
+  __shared__ T TS[(D == 3) ? NMAX * NMAX : 1];
   const int n = a.n0, n1 = n + 2;
   const int tot = (D == 3) ? n * n * n : n * n;
-  for (int w = threadIdx.x; w < tot; w += kBlock) {
+  const T* Tm = a.T0;  // 2D: the matrix stays in global memory (A and B fill the LDS)
+  if constexpr (D == 3) {
+    for (int w = threadIdx.x; w < n * n; w += kCoarseBlock) TS[w] = a.T0[w];
+    Tm = TS;
+  }
+  for (int w = threadIdx.x; w < tot; w += kCoarseBlock) {
     const int x = w % n, y = (w / n) % n, z = (D == 3) ? w / (n * n) : -1;
     A[w] = a.b[(size_t)(x + 1) + (size_t)n1 * ((size_t)(y + 1) + (size_t)n1 * (size_t)(z + 1))];
   }
   __syncthreads();
-  coarse_lines<T, D>(a, A, B, 0, true);
+  coarse_lines<T, D>(Tm, n, A, B, 0, true);
   __syncthreads();
-  coarse_lines<T, D>(a, B, A, 1, true);
+  coarse_lines<T, D>(Tm, n, B, A, 1, true);
   __syncthreads();
   T* cur = A;
   T* oth = B;
   if (D == 3) {
-    coarse_lines<T, D>(a, A, B, 2, true);
+    coarse_lines<T, D>(Tm, n, A, B, 2, true);
     __syncthreads();
     cur = B;
     oth = A;
   }
-  for (int w = threadIdx.x; w < tot; w += kBlock) {
+  for (int w = threadIdx.x; w < tot; w += kCoarseBlock) {
     const int x = w % n, y = (w / n) % n, z = (D == 3) ? w / (n * n) : 0;
     T l = a.lam[x] + a.lam[y];
     if (D == 3) l += a.lam[z];
@@ -207,16 +215,16 @@ __global__ void __launch_bounds__(kBlock) coarse_fdm_kernel(const CoarseArgs<T, 
   }
   __syncthreads();
   if (D == 3) {
-    coarse_lines<T, D>(a, cur, oth, 2, false);
+    coarse_lines<T, D>(Tm, n, cur, oth, 2, false);
     __syncthreads();
     T* t = cur; cur = oth; oth = t;
   }
-  coarse_lines<T, D>(a, cur, oth, 1, false);
+  coarse_lines<T, D>(Tm, n, cur, oth, 1, false);
   __syncthreads();
-  coarse_lines<T, D>(a, oth, cur, 0, false);
+  coarse_lines<T, D>(Tm, n, oth, cur, 0, false);
   __syncthreads();
   const int all = (D == 3) ? n1 * n1 * n1 : n1 * n1;
-  for (int w = threadIdx.x; w < all; w += kBlock) {
+  for (int w = threadIdx.x; w < all; w += kCoarseBlock) {
     const int x = w % n1, y = (w / n1) % n1, z = (D == 3) ? w / (n1 * n1) : 1;
     const bool inside = x > 0 && x < n1 - 1 && y > 0 && y < n1 - 1 && (D == 2 || (z > 0 && z < n1 - 1));
     a.x[w] = inside ? cur[(x - 1) + n * ((y - 1) + n * (D == 3 ? z - 1 : 0))] : T(0);
@@ -329,7 +337,7 @@ hipError_t launch_coarse_fdm(const CoarseFdmLaunch& L, hipStream_t s) {
   a.T0 = (const T*)L.T0;
   a.lam = (const T*)L.lam0;
   if (L.n0 > CoarseArgs<T, D>::NMAX || L.n0 < 1) return hipErrorInvalidValue;
-  coarse_fdm_kernel<T, D><<<1, kBlock, 0, s>>>(a);
+  coarse_fdm_kernel<T, D><<<1, kCoarseBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 template hipError_t launch_coarse_fdm<double, 2>(const CoarseFdmLaunch&, hipStream_t);
