@@ -113,8 +113,9 @@ typedef struct {
                             patches of a color per wavefront in the smoother: 1 = one
                             patch; 2 = two x-adjacent patches that share a closure face
                             (their boundary columns are loaded together); 0 = automatic
-                            (2, except 1 for FP32 at degree 4).  Same update either
-                            way, different rounding order */
+                            (2 on levels of at least 32 cells per direction, except
+                            FP32 at degree 4; 1 otherwise).  Same update either way,
+                            different rounding order */
   int vcycle_graph;      /* 1: the finest-level V-cycle of vps_vcycle and vps_solve is
                             captured once per (input, output) buffer pair into a HIP
                             graph on a stream of the library's own and replayed on the

@@ -394,9 +394,11 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   P.coef = coef;
   P.pb = c->cfg.patches_per_block;  // 0: the launcher chooses
   P.order = c->cfg.patch_order;
-  // automatic: pairs, except FP32 at degree 4 (there one patch per wave is as fast on
-  // whole colors and faster in slab batches, measured at 513^3)
-  const bool pair_auto = !(t == VPS_F32 && c->cfg.degree == 4);
+  // automatic: pairs on levels of at least 32 cells per direction (below, a color has
+  // too few patches to fill the chip twice over and one patch per wave finishes
+  // sooner), except FP32 at degree 4 (there one patch per wave is as fast on whole
+  // colors and faster in slab batches, measured at 513^3)
+  const bool pair_auto = L.ncell >= 32 && !(t == VPS_F32 && c->cfg.degree == 4);
   P.ppw = pair_kernel_applies(c->cfg) && (c->cfg.patches_per_wave == 2 || (c->cfg.patches_per_wave == 0 && pair_auto))
               ? 2 : 1;
   P.vlo = vlo;

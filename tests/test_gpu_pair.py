@@ -64,12 +64,13 @@ def test_pair_sweep_fp32(vps, k, N, reverse):
     assert rel(out[2], out[1]) <= 2e-5
 
 
-@pytest.mark.parametrize("dtype,k,auto", [("f32", 4, 1), ("f32", 3, 2), ("f64", 4, 2), ("f64", 2, 2)])
-def test_automatic_patches_per_wave(vps, dtype, k, auto):
-    """patches_per_wave=0 takes pairs except FP32 at degree 4: the same bits as that choice made explicit."""
+@pytest.mark.parametrize("dtype,k,N,auto", [("f32", 4, 32, 1), ("f32", 3, 32, 2), ("f64", 4, 32, 2), ("f64", 2, 32, 2),
+                                          ("f64", 4, 16, 1), ("f32", 3, 9, 1)])
+def test_automatic_patches_per_wave(vps, dtype, k, N, auto):
+    """patches_per_wave=0 takes pairs on levels of 32+ cells except FP32 at degree 4: the same bits as that
+    choice made explicit."""
     import torch
-    N = 9
-    say("automatic patches per wave", dtype, k)
+    say("automatic patches per wave", dtype, k, N)
     tdt = torch.float32 if dtype == "f32" else torch.float64
     b = vi.seeded_vector(3, k, N, 75)
     u0 = vi.seeded_vector(3, k, N, 76)
