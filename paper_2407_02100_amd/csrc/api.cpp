@@ -35,7 +35,7 @@ struct Level {
   Mat Mfull, Kfull, Mh[2], Kh[2];
   Mat T1;                   // FDM eigenvectors (q x q)
   std::vector<double> lam;  // FDM eigenvalues (q)
-  std::vector<double> lam_int;  // the same in the even/odd mode order (3D)
+  std::vector<double> lam_int;  // the same in the even/odd mode order
   Mat Te, To;               // even/odd blocks of T1 (symmetric / antisymmetric modes)
   Mat opM, opK;             // operator tile blocks
   Mat restrictG;            // transfer tile: this level -> level-1
@@ -267,8 +267,8 @@ void build_level(Level& L, int k, int d, int ncell) {
   vps::gen_eig(q, Mi, Ki, &L.T1, &L.lam);
   std::vector<int> order;
   if (!vps::fdm_even_odd(q, L.T1, &L.Te, &L.To, &order)) {
-    L.Te.clear();  // no even/odd structure: the one-patch-per-wave kernel is not used
-  } else if (d == 3) {
+    L.Te.clear();  // no even/odd structure: the one-patch-per-wave kernels are not used
+  } else {
     L.lam_int.resize(q);
     for (int j = 0; j < q; ++j) L.lam_int[j] = L.lam[order[j]];
   }
@@ -401,6 +401,7 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   const bool pair_auto = L.ncell >= 32 && !(t == VPS_F32 && c->cfg.degree == 4);
   P.ppw = pair_kernel_applies(c->cfg) && (c->cfg.patches_per_wave == 2 || (c->cfg.patches_per_wave == 0 && pair_auto))
               ? 2 : 1;
+  P.row2 = c->cfg.wave_rows_2d;
   P.vlo = vlo;
   P.vhi = vhi;
   if (coef == VPS_COEF_CONST) {
@@ -754,6 +755,9 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.patches_per_wave < 0 || C.patches_per_wave > 2) return VPS_E_ARG;
   if (C.patches_per_wave == 2 && !pair_kernel_applies(C)) return VPS_E_UNSUPPORTED;
   if (C.vcycle_graph != 0 && C.vcycle_graph != 1) return VPS_E_ARG;
+  if (C.wave_rows_2d < 0 || C.wave_rows_2d > 2) return VPS_E_ARG;
+  if (C.wave_rows_2d == 1 && (C.dim != 2 || C.coef != VPS_COEF_CONST || C.degree < 2 || C.patches_per_block != 0))
+    return VPS_E_UNSUPPORTED;
   if (C.algorithm == VPS_ALG_SEPARATED && (C.dim != 3 || C.coef != VPS_COEF_CONST || C.degree < 2 || C.degree > 4))
     return VPS_E_UNSUPPORTED;
   // every node index must fit in int on the kernels' inner indexing

@@ -41,6 +41,7 @@ struct PatchLaunch {
   const double* lam_int;  // Q eigenvalues in the even/odd mode order (host), or null
   int order;              // vps_config.patch_order (3D one-patch-per-wave kernel)
   int ppw;                // 3D, rho = 1, K = 2..4: patches per wavefront (1 or 2)
+  int row2;               // 2D, rho = 1, K = 2..5: row of patches per wave (0 automatic, 1 always, 2 never)
   int vlo, vhi;           // vertex range (inclusive) in the slowest direction; vhi = 0: all vertices
 };
 

@@ -5,6 +5,7 @@
 #include "kernels.h"
 #include "patch_wave.h"
 #include "patch_pair.h"
+#include "patch_row2.h"
 #include "patch_solve.h"
 #include "launch.h"
 
@@ -68,6 +69,39 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
     }
   for (int i = 0; i < Q * Q; ++i) a.m.T1[i] = (T)L.T1[i];
   for (int i = 0; i < Q; ++i) a.m.lam[i] = (T)L.lam[i];
+  // 2D, rho = 1: a row of patches per wave where it is measured faster than the
+  // LDS-staged kernel (degree 2 from 256 cells per direction, degree 3 from 512;
+  // its x contraction reads (2K-1)(2K+1) LDS values per lane, too many above)
+  const bool row2 = L.row2 == 1 || (L.row2 == 0 && ((K == 2 && N >= 256) || (K == 3 && N >= 512)));
+  if (D == 2 && L.coef == 0 && L.pb == 0 && L.Te && L.lam_int && row2) {
+    if constexpr (K >= 2 && K <= 5) {  // a row of patches per wave
+      static_assert(sizeof(RowArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
+      using R = RowShape<K>;
+      RowArgs<T, K> w;
+      w.u = a.u;
+      w.b = a.b;
+      w.n1 = a.n1;
+      for (int e = 0; e < 2; ++e) {
+        w.v0[e] = a.v0[e];
+        w.np[e] = a.np[e];
+      }
+      w.ngx = (a.np[0] + R::G - 1) / R::G;
+      const unsigned long long ng = (unsigned long long)w.ngx * (unsigned)a.np[1];
+      if (ng * (unsigned)w.ngx >= (1ull << 32)) return hipErrorInvalidValue;  // exact division by ngx
+      w.ngroups = (unsigned)ng;
+      const unsigned long long vbytes = (unsigned long long)a.n1 * a.n1 * sizeof(T);
+      if (vbytes >= (1ull << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
+      w.vec_bytes = (unsigned)vbytes;
+      w.magic_g = magic_of((unsigned)w.ngx);
+      if (!make_band<T, K>(L.M[0], L.Kst[0], &w.band)) return hipErrorInvalidValue;
+      for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
+      for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
+      for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];
+      const unsigned grid = (w.ngroups + kXcd - 1) / kXcd * kXcd;  // a multiple of the XCD count
+      patch_row2_kernel<T, K><<<grid, 64, 0, s>>>(w);
+      return hipGetLastError();
+    }
+  }
   if (D == 3 && L.coef == 0 && L.pb == 0) {
     if constexpr (K >= 2 && K <= 4) {  // (2K-1)^2 interior lines must fit the 64 lanes of a wave
       static_assert(sizeof(WaveArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");

@@ -38,7 +38,7 @@ class vps_config(ctypes.Structure):
                 ("vcycle_dtype", ctypes.c_int), ("coef", ctypes.c_int), ("patches_per_block", ctypes.c_int),
                 ("stream_min_cells", ctypes.c_int), ("algorithm", ctypes.c_int), ("patch_order", ctypes.c_int),
                 ("batch_layers", ctypes.c_int), ("patches_per_wave", ctypes.c_int),
-                ("vcycle_graph", ctypes.c_int)]
+                ("vcycle_graph", ctypes.c_int), ("wave_rows_2d", ctypes.c_int)]
 
 
 class vps_solve_info(ctypes.Structure):
@@ -162,10 +162,11 @@ class Context:
 
     def __init__(self, dim, degree, n_cells, n_levels, pre=1, post=1, vcycle_dtype="f64",
                  coef="const", patches_per_block=0, stream=None, stream_min_cells=0, algorithm="combined",
-                 patch_order=0, batch_layers=0, patches_per_wave=0, vcycle_graph=False):
+                 patch_order=0, batch_layers=0, patches_per_wave=0, vcycle_graph=False, wave_rows_2d=0):
         cfg = vps_config(dim, degree, n_cells, n_levels, pre, post, _DTYPE[vcycle_dtype], _COEF[coef],
                          patches_per_block, stream_min_cells, _ALGORITHM[algorithm], patch_order, batch_layers,
-                         patches_per_wave, int(bool(vcycle_graph)))
+                         patches_per_wave, int(bool(vcycle_graph)),
+                         wave_rows_2d)
         self.cfg = cfg
         self.dim, self.degree, self.n_levels = dim, degree, n_levels
         h = _vp()

@@ -61,6 +61,9 @@ def test_status_strings(lib):
     (dict(dim=3, degree=4, n_cells=204, n_levels=2), -2),  # 817^3 FP64 values exceed 32-bit byte offsets
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=3), -1),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, vcycle_graph=2), -1),
+    (dict(dim=2, degree=2, n_cells=8, n_levels=2, wave_rows_2d=3), -1),
+    (dict(dim=3, degree=2, n_cells=8, n_levels=2, wave_rows_2d=1), -2),   # row kernel: 2D only
+    (dict(dim=2, degree=1, n_cells=8, n_levels=2, wave_rows_2d=1), -2),   # row kernel: degree >= 2
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=-1), -1),
     (dict(dim=2, degree=2, n_cells=8, n_levels=2, patches_per_wave=2), -2),   # pairs: 3D only
     (dict(dim=3, degree=1, n_cells=8, n_levels=2, patches_per_wave=2), -2),   # pairs: degree 2..4
@@ -74,7 +77,7 @@ def test_create_rejects_invalid_configurations(lib, cfg, status):
     c = vps.vps_config(cfg["dim"], cfg["degree"], cfg["n_cells"], cfg["n_levels"], cfg.get("pre", 1), 1, 0, 0,
                        cfg.get("patches_per_block", 0), cfg.get("stream_min_cells", 0), cfg.get("algorithm", 0),
                        cfg.get("patch_order", 0), cfg.get("batch_layers", 0), cfg.get("patches_per_wave", 0),
-                       cfg.get("vcycle_graph", 0))
+                       cfg.get("vcycle_graph", 0), cfg.get("wave_rows_2d", 0))
     h = ctypes.c_void_p()
     st = vps.lib().vps_create(ctypes.byref(c), None, ctypes.byref(h))
     assert st == status
