@@ -125,10 +125,10 @@ typedef struct {
   int wave_rows_2d;      /* 2D, rho = 1, degree 2..5, automatic patches_per_block: the
                             smoother kernel.  0 = automatic: a row of x-adjacent
                             patches of a color per wavefront (their shared closure
-                            columns loaded once, as rows of up to 61 values) at degree
-                            2 from 256 cells per direction and degree 3 from 512, the
-                            LDS-staged kernel otherwise; 1 = always the row kernel;
-                            2 = never.  Same update, different rounding order */
+                            columns loaded once, as rows of up to 61 values) on levels
+                            of at least 64 cells per direction, the LDS-staged kernel
+                            below; 1 = always the row kernel; 2 = never.  Same
+                            update, different rounding order */
 } vps_config;
 
 typedef struct {

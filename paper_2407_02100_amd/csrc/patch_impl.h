@@ -69,10 +69,10 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
     }
   for (int i = 0; i < Q * Q; ++i) a.m.T1[i] = (T)L.T1[i];
   for (int i = 0; i < Q; ++i) a.m.lam[i] = (T)L.lam[i];
-  // 2D, rho = 1: a row of patches per wave where it is measured faster than the
-  // LDS-staged kernel (degree 2 from 256 cells per direction, degree 3 from 512;
-  // its x contraction reads (2K-1)(2K+1) LDS values per lane, too many above)
-  const bool row2 = L.row2 == 1 || (L.row2 == 0 && ((K == 2 && N >= 256) || (K == 3 && N >= 512)));
+  // 2D, rho = 1: a row of patches per wave from 64 cells per direction (measured
+  // faster than the LDS-staged kernel there for every degree 2..5; below, both
+  // are launch-latency bound)
+  const bool row2 = L.row2 == 1 || (L.row2 == 0 && N >= 64);
   if (D == 2 && L.coef == 0 && L.pb == 0 && L.Te && L.lam_int && row2) {
     if constexpr (K >= 2 && K <= 5) {  // a row of patches per wave
       static_assert(sizeof(RowArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");

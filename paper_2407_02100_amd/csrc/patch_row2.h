@@ -18,12 +18,16 @@ namespace vps {
 //
 // Stages of the wave that owns G patches of one color row:
 //   1. lanes = closure columns: every load (closure rows of u; the
-//      right-hand side goes straight to the lanes of stage 2), y contraction
-//      of the column (interior rows taken as zero off the face columns);
-//   2. lanes = (patch, interior column): x contraction from LDS, local
-//      residual, T^T along y in registers;
-//   3. lanes = (patch, y mode): T^T along x, 1/Lambda, T along x;
-//   4. lanes = (patch, interior column): T along y, store the column.
+//      right-hand side into the lanes (patch, interior column)), y
+//      contraction of the column (interior rows taken as zero off the face
+//      columns); the right-hand side into LDS;
+//   2. lanes = (patch, interior row): x contraction of the row from LDS,
+//      local residual, T^T along x in registers;
+//   3. lanes = (patch, x mode): T^T along y, 1/Lambda;
+//   4. lanes = (patch, y mode): T along x;
+//   5. lanes = (patch, interior column): T along y, store the column.
+// Each lane keeps one line in registers at a time; between stages the lines
+// change direction through LDS.
 
 template <int K>
 struct RowShape {
@@ -52,10 +56,10 @@ struct RowArgs {
 template <typename T, int K>
 __global__ void __launch_bounds__(64) patch_row2_kernel(const RowArgs<T, K> a) {
   using R = RowShape<K>;
-  constexpr int P = R::P, Q = R::Q, S = R::S, G = R::G, C = R::C, GQ = G * Q;
-  __shared__ T ZM[Q * C];     // [oy][column] after the y contraction: M_y u
-  __shared__ T ZK[Q * C];     // ... and K_y u
-  __shared__ T W[G * Q * Q];  // [patch][x][y mode]
+  constexpr int P = R::P, Q = R::Q, S = R::S, G = R::G, C = R::C, GQ = G * Q, Q2 = Q * Q;
+  __shared__ T ZM[Q * C];    // [oy][column] after the y contraction: M_y u
+  __shared__ T ZK[Q * C];    // ... and K_y u
+  __shared__ T W[G * Q2];    // [patch][.][.]: right-hand side, then the transposes of the FDM
 
   const unsigned h = blockIdx.x;
   const unsigned per = gridDim.x / kXcd;
@@ -82,13 +86,13 @@ __global__ void __launch_bounds__(64) patch_row2_kernel(const RowArgs<T, K> a) {
 #pragma unroll
   for (int y = 0; y < P; ++y) uc[y] = buf_load<T>(ur, (unsigned)col * (unsigned)sizeof(T), sbase + srow * y);
   const int l2 = min(lane, GQ - 1);
-  const int p2 = l2 / Q, x2 = l2 % Q;  // (patch, interior column) of stages 2 and 4
-  const unsigned off2 = (unsigned)min(p2 * S + 1 + x2, cmax) * (unsigned)sizeof(T);
+  const int pp = l2 / Q, ll = l2 % Q;  // (patch, line) of stages 2-5
+  const unsigned off2 = (unsigned)min(pp * S + 1 + ll, cmax) * (unsigned)sizeof(T);
   T bv[Q];
 #pragma unroll
   for (int o = 0; o < Q; ++o) bv[o] = buf_load<T>(br, off2, sbase + srow * (o + 1));
 
-  // ---- 1. y contraction of the closure columns ----
+  // ---- 1. y contraction of the closure columns; right-hand side into W[p][oy][ox] ----
   if (lane < C) {
     if (lane % S != 0) {  // a column inside a patch: its interior rows count as zero
 #pragma unroll
@@ -108,57 +112,77 @@ __global__ void __launch_bounds__(64) patch_row2_kernel(const RowArgs<T, K> a) {
       ZK[o * C + lane] = zk;
     }
   }
+  if (lane < GQ) {
+#pragma unroll
+    for (int o = 0; o < Q; ++o) W[(pp * Q + o) * Q + ll] = bv[o];
+  }
   __syncthreads();
 
-  // ---- 2. x contraction, local residual, T^T along y  (lanes (patch, ox)) ----
+  // ---- 2. x contraction of row oy, local residual, T^T along x  (lanes (patch, oy)) ----
   if (lane < GQ) {
-    const int j = x2 + 1, c0 = p2 * S;
-    T r[Q], m[Q];
+    const int oy = ll, c0 = pp * S;
+    T zm[P], zk[P], r[Q], m[Q];
+#pragma unroll
+    for (int x = 0; x < P; ++x) {
+      zm[x] = ZM[oy * C + c0 + x];
+      zk[x] = ZK[oy * C + c0 + x];
+    }
 #pragma unroll
     for (int o = 0; o < Q; ++o) {
+      const int j = o + 1;
       T acc = T(0);
 #pragma unroll
       for (int x = 0; x < P; ++x) {
         if (x < band_lo(j, K) || x > band_hi(j, K)) continue;
-        acc = fma(band_k(a.band, j, x), ZM[o * C + c0 + x], acc);
-        acc = fma(band_m(a.band, j, x), ZK[o * C + c0 + x], acc);
+        acc = fma(band_k(a.band, j, x), zm[x], acc);
+        acc = fma(band_m(a.band, j, x), zk[x], acc);
       }
-      r[o] = bv[o] - acc;
+      r[o] = W[(pp * Q + oy) * Q + o] - acc;
     }
     fdm_forward<T, K>(a.f, r, m);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) W[(p2 * Q + x2) * Q + q] = m[q];
+    for (int q = 0; q < Q; ++q) W[(pp * Q + oy) * Q + q] = m[q];  // the lane's own row: [p][oy][mx]
   }
   __syncthreads();
 
-  // ---- 3. T^T along x, 1/Lambda, T along x  (lanes (patch, my)) ----
+  // ---- 3. T^T along y, 1/Lambda  (lanes (patch, mx)) ----
   if (lane < GQ) {
-    const int my = x2;
-    T v[Q], c[Q], d[Q];
+    const int mx = ll;
+    T v[Q], c[Q];
 #pragma unroll
-    for (int x = 0; x < Q; ++x) v[x] = W[(p2 * Q + x) * Q + my];
+    for (int y = 0; y < Q; ++y) v[y] = W[(pp * Q + y) * Q + mx];
     fdm_forward<T, K>(a.f, v, c);
-    T lmy = a.lam[0];
+    T lmx = a.lam[0];
 #pragma unroll
-    for (int q = 1; q < Q; ++q) lmy = (my == q) ? a.lam[q] : lmy;
+    for (int q = 1; q < Q; ++q) lmx = (mx == q) ? a.lam[q] : lmx;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      if constexpr (sizeof(T) == 4) c[q] *= __builtin_amdgcn_rcpf(lmy + a.lam[q]);
-      else c[q] /= (lmy + a.lam[q]);
+    for (int q = 0; q < Q; ++q) {  // the lane's own column: [p][my][mx]
+      if constexpr (sizeof(T) == 4) W[(pp * Q + q) * Q + mx] = c[q] * __builtin_amdgcn_rcpf(lmx + a.lam[q]);
+      else W[(pp * Q + q) * Q + mx] = c[q] / (lmx + a.lam[q]);
     }
-    fdm_backward<T, K>(a.f, c, d);
-#pragma unroll
-    for (int x = 0; x < Q; ++x) W[(p2 * Q + x) * Q + my] = d[x];
   }
   __syncthreads();
 
-  // ---- 4. T along y, store the new interior column  (lanes (patch, ox)) ----
+  // ---- 4. T along x  (lanes (patch, my)) ----
   if (lane < GQ) {
+    const int my = ll;
     T c[Q], d[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) c[q] = W[(p2 * Q + x2) * Q + q];
+    for (int q = 0; q < Q; ++q) c[q] = W[(pp * Q + my) * Q + q];
     fdm_backward<T, K>(a.f, c, d);
-    if (p2 < nact) {
+#pragma unroll
+    for (int x = 0; x < Q; ++x) W[(pp * Q + my) * Q + x] = d[x];  // the lane's own row: [p][my][x]
+  }
+  __syncthreads();
+
+  // ---- 5. T along y, store the new interior column  (lanes (patch, x)) ----
+  if (lane < GQ) {
+    const int x = ll;
+    T c[Q], d[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) c[q] = W[(pp * Q + q) * Q + x];
+    fdm_backward<T, K>(a.f, c, d);
+    if (pp < nact) {
 #pragma unroll
       for (int y = 0; y < Q; ++y) buf_store<T>(d[y], ur, off2, sbase + srow * (y + 1));
     }
