@@ -463,6 +463,10 @@ hipError_t do_operator(vps_context* c, int l, const void* u, const void* b, void
     vps::StreamLaunch S{u, b, out, L.n1, L.n1, L.ncell, L.sG0.data(), L.sG1.data(), L.sZ0.data(), L.sZ1.data()};
     return dispatch_tk(t, k, [&]<typename TT, int K>() { return vps::launch_stream_operator<TT, K>(S, c->stream); });
   }
+  if (c->cfg.coef == VPS_COEF_CONST && d == 2 && L.ncell >= stream_min(c)) {
+    vps::Stream2Launch S{u, b, out, L.n1, L.ncell, L.Mc.data(), L.Kc.data()};
+    return dispatch_tk(t, k, [&]<typename TT, int K>() { return vps::launch_stream2_operator<TT, K>(S, c->stream); });
+  }
   if (c->cfg.coef == VPS_COEF_CONST) {
     vps::TileLaunch T{};
     T.in = u;

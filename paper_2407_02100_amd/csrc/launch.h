@@ -61,6 +61,18 @@ struct TileLaunch {
   const double* G1;  // NO x NI (operator stiffness) or null
 };
 
+// Row-streaming 2D operator / residual (constant coefficient).
+struct Stream2Launch {
+  const void* in;
+  const void* b;   // r = b - A u when non-null
+  void* out;
+  int n1, ncell;
+  const double* Mc;  // (K+1) x (K+1) cell mass matrix (h-scaled)
+  const double* Kc;  // ... and stiffness matrix
+};
+template <typename T, int K>
+hipError_t launch_stream2_operator(const Stream2Launch& L, hipStream_t s);
+
 // Plane-streaming 3D kernels (constant coefficient): operator / residual and restriction.
 struct StreamLaunch {
   const void* in;
