@@ -6,6 +6,7 @@
 #include "patch_wave.h"
 #include "patch_pair.h"
 #include "patch_row2.h"
+#include "patch_big.h"
 #include "patch_solve.h"
 #include "launch.h"
 
@@ -99,6 +100,35 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
       for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];
       const unsigned grid = (w.ngroups + kXcd - 1) / kXcd * kXcd;  // a multiple of the XCD count
       patch_row2_kernel<T, K><<<grid, 64, 0, s>>>(w);
+      return hipGetLastError();
+    }
+  }
+  if (D == 3 && L.coef == 0 && L.pb == 0 && L.order == 0 && L.Te && L.lam_int) {
+    if constexpr (K == 5) {  // one patch per wave, the interior lines in passes of 64
+      static_assert(sizeof(BigArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
+      BigArgs<T, K> w;
+      w.u = a.u;
+      w.b = a.b;
+      w.n1 = a.n1;
+      for (int e = 0; e < 3; ++e) {
+        w.v0[e] = a.v0[e];
+        w.np[e] = a.np[e];
+      }
+      w.npatch = (unsigned)a.np[0] * (unsigned)a.np[1] * (unsigned)a.np[2];
+      if ((unsigned long long)w.npatch * (unsigned)a.np[0] >= (1ull << 32) ||
+          (unsigned long long)w.npatch * (unsigned)a.np[1] >= (1ull << 32))
+        return hipErrorInvalidValue;  // exact division by np[0] and np[1]
+      const unsigned long long vbytes = (unsigned long long)a.n1 * a.n1 * a.n1 * sizeof(T);
+      if (vbytes >= (1ull << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
+      w.vec_bytes = (unsigned)vbytes;
+      w.magic_x = magic_of((unsigned)a.np[0]);
+      w.magic_y = magic_of((unsigned)a.np[1]);
+      if (!make_band<T, K>(L.M[0], L.Kst[0], &w.band)) return hipErrorInvalidValue;
+      for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
+      for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
+      for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];
+      const unsigned grid = (w.npatch + kXcd - 1) / kXcd * kXcd;  // a multiple of the XCD count
+      patch_big3_kernel<T, K><<<grid, 64, 0, s>>>(w);
       return hipGetLastError();
     }
   }

@@ -144,3 +144,41 @@ def test_single_patch_domain_fp64(vps, k, form):
         got = host(u)
     assert rel(got, want) <= 1e-12
     assert np.abs(b - A @ got).max() <= 1e-10 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("N", [5, 6, 9])
+def test_degree5_one_patch_kernel_fp64(vps, N):
+    """k = 5: one patch per wave with the 81 interior lines in two passes; every color against the oracle."""
+    say("degree 5 one-patch kernel", N)
+    k = 5
+    A = assemble.assemble_kron(3, k, N)
+    P = smoother.Patches(3, k, N)
+    S = smoother.LocalSolvers(A, P, "shared")
+    b = vi.seeded_vector(3, k, N, 83)
+    uo = vi.seeded_vector(3, k, N, 84)
+    with vps.Context(3, k, N, 1) as ctx:
+        u = dev(uo)
+        bd = dev(b)
+        for c in range(8):
+            ctx.smooth_color(0, u, bd, c)
+            uo = smoother.apply_color(A, b, uo, P, S, c)
+            assert rel(host(u), uo) <= 1e-12, (c, rel(host(u), uo))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_degree5_matches_generic_kernel(vps, dtype):
+    """k = 5 sweeps, forward and reverse: the one-patch kernel against the LDS-staged generic kernel."""
+    import torch
+    k, N = 5, 12
+    say("degree 5 vs generic", dtype)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    b = vi.seeded_vector(3, k, N, 85)
+    u0 = vi.seeded_vector(3, k, N, 86)
+    out = []
+    for pb in (0, 1):
+        with vps.Context(3, k, N, 1, vcycle_dtype=dtype, patches_per_block=pb) as ctx:
+            u = dev(u0, tdt)
+            ctx.smooth(0, u, dev(b, tdt), sweeps=1)
+            ctx.smooth(0, u, dev(b, tdt), sweeps=1, reverse=True)
+            out.append(host(u))
+    assert rel(out[0], out[1]) <= (1e-12 if dtype == "f64" else 2e-5)
