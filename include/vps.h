@@ -86,7 +86,9 @@ typedef struct {
   int coef;              /* vps_coef */
   int patches_per_block; /* 0 = automatic (3D rho = 1: one patch per wavefront);
                             1, 2, 4 = batches of that many patches along x per
-                            256-thread workgroup */
+                            256-thread workgroup of the LDS-staged kernel
+                            (VPS_E_UNSUPPORTED where the batch exceeds the LDS
+                            in the V-cycle dtype) */
   int stream_min_cells;  /* 3D: the operator and the residual (rho = 1) and the
                             grid transfers use the plane-streaming kernels on
                             levels with at least this many cells per direction

@@ -751,6 +751,10 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.vcycle_dtype != VPS_F64 && C.vcycle_dtype != VPS_F32) return VPS_E_ARG;
   if (C.coef < VPS_COEF_CONST || C.coef > VPS_COEF_CELL_LEARNED) return VPS_E_ARG;
   if (C.patches_per_block != 0 && !vps::valid_patches_per_block(C.patches_per_block)) return VPS_E_UNSUPPORTED;
+  if (C.patches_per_block != 0 && C.dim >= 2 && C.dim <= 3 && C.degree >= 1 && C.degree <= 5 &&
+      C.coef >= VPS_COEF_CONST && C.coef <= VPS_COEF_CELL_LEARNED &&
+      !vps::patches_per_block_fits(C.degree, C.dim, C.coef, C.patches_per_block, C.vcycle_dtype == VPS_F64))
+    return VPS_E_UNSUPPORTED;  // that batch of patches exceeds the workgroup LDS
   if (C.stream_min_cells < 0) return VPS_E_ARG;
   if (C.algorithm != VPS_ALG_COMBINED && C.algorithm != VPS_ALG_SEPARATED) return VPS_E_ARG;
   if (C.patch_order < 0 || C.patch_order > 3) return VPS_E_ARG;

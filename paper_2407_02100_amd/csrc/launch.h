@@ -20,6 +20,8 @@ constexpr int prolong_tc(int K, int D) { return D == 2 ? 2 : (K <= 2 ? 2 : 1); }
 int default_patches_per_block(int K, int D, int coef, bool fp64);
 // Supported explicit choices.
 bool valid_patches_per_block(int pb);
+// Whether the LDS-staged kernel with that batch fits the workgroup LDS.
+bool patches_per_block_fits(int K, int D, int coef, int pb, bool fp64);
 
 struct PatchLaunch {
   void* u;

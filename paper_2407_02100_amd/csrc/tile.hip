@@ -179,6 +179,10 @@ static int patch_lds_bytes(int K, int D, int coef, int pb, bool fp64) {
 
 bool valid_patches_per_block(int pb) { return pb == 1 || pb == 2 || pb == 4; }
 
+bool patches_per_block_fits(int K, int D, int coef, int pb, bool fp64) {
+  return patch_lds_bytes(K, D, coef, pb, fp64) + 4096 <= 65536;
+}
+
 int default_patches_per_block(int K, int D, int coef, bool fp64) {
   // the largest batch whose LDS stays below 40 KiB (room for 3+ workgroups per CU)
   for (int pb : {4, 2, 1})

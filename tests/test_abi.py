@@ -50,6 +50,7 @@ def test_status_strings(lib):
     (dict(dim=3, degree=2, n_cells=12, n_levels=4), -2),   # 12 not divisible by 8
     (dict(dim=3, degree=2, n_cells=8, n_levels=4), -2),    # coarsest level has 1 cell
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_block=3), -2),
+    (dict(dim=3, degree=5, n_cells=8, n_levels=2, patches_per_block=2), -2),  # exceeds the LDS in FP64
     (dict(dim=2, degree=2, n_cells=8, n_levels=2, pre=-1), -1),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, stream_min_cells=-1), -1),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, algorithm=2), -1),
