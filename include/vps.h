@@ -89,12 +89,13 @@ typedef struct {
                             256-thread workgroup of the LDS-staged kernel
                             (VPS_E_UNSUPPORTED where the batch exceeds the LDS
                             in the V-cycle dtype) */
-  int stream_min_cells;  /* 3D: the operator and the residual (rho = 1) and the
-                            grid transfers use the plane-streaming kernels on
-                            levels with at least this many cells per direction
-                            (for a transfer: on its coarse level), single-pass
-                            tile kernels below; 0 = default (32), 1 = always;
-                            must be >= 0 */
+  int stream_min_cells;  /* the operator and the residual (rho = 1) and the grid
+                            transfers use the plane- (3D) or row-streaming (2D)
+                            kernels on levels with at least this many cells per
+                            direction (for a transfer: on its coarse level),
+                            single-pass tile kernels below; 0 = default (32; 2D
+                            transfers 256, and the 2D restriction keeps the tiles
+                            at degree 5), 1 = always; must be >= 0 */
   int algorithm;         /* vps_algorithm of every smoothing step (vps_smooth_color,
                             vps_smooth, the V-cycle) */
   int patch_order;       /* 3D, rho = 1, one patch per wavefront: order in which the

@@ -373,6 +373,10 @@ int stream_min(const vps_context* c) {
   return c->cfg.stream_min_cells > 0 ? c->cfg.stream_min_cells : 32;
 }
 
+// 2D grid transfers: the row-streaming kernels on coarse levels of at least this many
+// cells (vps_config.stream_min_cells when set, 256 otherwise)
+int stream2_transfer_min(const vps_context* c) { return c->cfg.stream_min_cells > 0 ? c->cfg.stream_min_cells : 256; }
+
 vps_dtype vdt(const vps_context* c) { return (vps_dtype)c->cfg.vcycle_dtype; }
 
 // ---- level operations (dtype t) ----
@@ -500,6 +504,14 @@ hipError_t do_restrict(vps_context* c, int l, const void* rf, void* rc, vps_dtyp
                         L.rZ.data(), nullptr};
     return dispatch_tk(t, k, [&]<typename TT, int K>() { return vps::launch_stream_restrict<TT, K>(S, c->stream); });
   }
+  // 2D: the row-streaming restriction walks coarse cells one fine row at a time, which
+  // pays from 256 coarse cells per direction and up to degree 4 (measured; below, and
+  // at degree 5, the single-pass tiles are faster)
+  if (d == 2 && k <= 4 && c->lv[l - 1].ncell >= stream2_transfer_min(c)) {
+    const Level& L = c->lv[l];
+    vps::Stream2Launch S{rf, nullptr, rc, 0, c->lv[l - 1].ncell, L.rG.data(), L.rZ.data()};
+    return dispatch_tk(t, k, [&]<typename TT, int K>() { return vps::launch_stream2_restrict<TT, K>(S, c->stream); });
+  }
   vps::TileLaunch T{};
   T.in = rf;
   T.out = rc;
@@ -518,6 +530,11 @@ hipError_t do_prolong(vps_context* c, int l, const void* ec, void* uf, vps_dtype
     vps::StreamLaunch S{ec, nullptr, uf, c->lv[l - 1].n1, L.n1, c->lv[l - 1].ncell, L.pG.data(), nullptr,
                         L.pG.data(), nullptr};
     return dispatch_tk(t, k, [&]<typename TT, int K>() { return vps::launch_stream_prolong<TT, K>(S, c->stream); });
+  }
+  if (d == 2 && c->lv[l - 1].ncell >= stream2_transfer_min(c)) {  // 2D: from 256 coarse cells (measured)
+    const Level& L = c->lv[l];
+    vps::Stream2Launch S{ec, nullptr, uf, 0, c->lv[l - 1].ncell, L.pG.data(), nullptr};
+    return dispatch_tk(t, k, [&]<typename TT, int K>() { return vps::launch_stream2_prolong<TT, K>(S, c->stream); });
   }
   vps::TileLaunch T{};
   T.in = ec;

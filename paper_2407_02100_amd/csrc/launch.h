@@ -74,6 +74,13 @@ struct Stream2Launch {
 };
 template <typename T, int K>
 hipError_t launch_stream2_operator(const Stream2Launch& L, hipStream_t s);
+// 2D transfers on the same struct: ncell = coarse cells; restriction: Mc = the
+// restriction rows (K x (4K+1)), Kc = the coarse-cell block ((K+1) x (2K+1));
+// prolongation: Mc = the fine rows of one coarse cell (2K x (K+1)).
+template <typename T, int K>
+hipError_t launch_stream2_restrict(const Stream2Launch& L, hipStream_t s);
+template <typename T, int K>
+hipError_t launch_stream2_prolong(const Stream2Launch& L, hipStream_t s);
 
 // Plane-streaming 3D kernels (constant coefficient): operator / residual and restriction.
 struct StreamLaunch {

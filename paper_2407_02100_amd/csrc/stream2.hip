@@ -138,6 +138,177 @@ __global__ void __launch_bounds__(64) stream2_operator_kernel(const Op2Args<T, K
   if (c1 == a.ncell) emit(n1 - 1, carry);  // the last grid row (Dirichlet: zero)
 }
 
+// ---- restriction r_c = R r_f, R = P^T (1D factors along x and y) ----
+//
+// One wavefront owns a strip of 64 - 2K coarse output columns (one lane per
+// coarse column, K halo lanes on each side; a lane loads the two fine values
+// 2X and 2X + 1, so a fine row arrives as one contiguous run of 128 values)
+// and walks a chunk of coarse cell rows: the 2K fine rows of a coarse cell
+// are contracted along x from LDS with the lane's row of R and folded into
+// the cell's K + 1 coarse rows; the coarse vertex row shared by two cells is
+// carried.  A chunk starts one coarse cell early (the carry into its first
+// vertex row) and writes its own rows only.
+
+template <typename T, int K>
+struct Tr2Args {
+  const T* __restrict__ in;
+  T* __restrict__ out;
+  int n1f, n1c, ncc;         // fine and coarse nodes per direction, coarse cells
+  int strips, cz;            // column strips, coarse cell rows per chunk
+  unsigned nblocks;
+  unsigned bytes_in, bytes_out;
+  T g[K * (4 * K + 1)];      // restriction: R row of a coarse node at position a (0..K-1) over 4K+1 fine nodes
+  T z[(K + 1) * (2 * K + 1)];  // restriction: cell block [coarse i][fine l]; prolongation: P rows [fine j][coarse i]
+};
+
+template <typename T, int K>
+__global__ void __launch_bounds__(64) stream2_restrict_kernel(const Tr2Args<T, K> a) {
+  constexpr int GW = 4 * K + 1, ZW = 2 * K + 1, WO = 64 - 2 * K;
+  __shared__ T row[128];
+  const unsigned h = blockIdx.x;
+  const unsigned per = gridDim.x / kXcd;
+  const unsigned logical = (h % kXcd) * per + h / kXcd;
+  if (logical >= a.nblocks) return;
+  const int lane = threadIdx.x;
+  const int strip = (int)(logical % (unsigned)a.strips);
+  const int chunk = (int)(logical / (unsigned)a.strips);
+  const int c0 = chunk * a.cz, c1 = min(a.ncc, c0 + a.cz);
+  const int cs = max(c0 - 1, 0);
+  const int X = strip * WO - K + lane;  // this lane's coarse column
+  const bool out_lane = lane >= K && lane < 64 - K && X >= 0 && X < a.n1c;
+  const bool xdir = X == 0 || X == a.n1c - 1;
+  const __amdgpu_buffer_rsrc_t ir = make_rsrc(a.in, a.bytes_in);
+  const __amdgpu_buffer_rsrc_t orr = make_rsrc(a.out, a.bytes_out);
+  const int f0 = 2 * X, f1 = 2 * X + 1;  // the two fine columns this lane loads
+  const bool in0 = f0 >= 0 && f0 < a.n1f, in1 = f1 >= 0 && f1 < a.n1f;
+  const unsigned off0 = (unsigned)(in0 ? f0 : 0) * (unsigned)sizeof(T);
+  const unsigned off1 = (unsigned)(in1 ? f1 : 0) * (unsigned)sizeof(T);
+  const unsigned srf = (unsigned)a.n1f * (unsigned)sizeof(T), src = (unsigned)a.n1c * (unsigned)sizeof(T);
+  const unsigned xoff = (unsigned)(out_lane ? X : 0) * (unsigned)sizeof(T);
+
+  // the lane's row of R over fine offsets -2K..2K from 2X
+  T cg[GW];
+  {
+    const int al = ((X % K) + K) % K;
+#pragma unroll
+    for (int d = -2 * K; d <= 2 * K; ++d) {
+      T v = T(0);
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const int i = d + 2 * K + 2 * q;  // index into the 4K+1 window of position q
+        if (i >= 0 && i < GW) v = (al == q) ? a.g[q * GW + i] : v;
+      }
+      cg[d + 2 * K] = v;
+    }
+  }
+  auto xrow = [&](int y) {
+    const T v0 = in0 ? buf_load<T>(ir, off0, srf * (unsigned)y) : T(0);
+    const T v1 = in1 ? buf_load<T>(ir, off1, srf * (unsigned)y) : T(0);
+    row[2 * lane] = v0;
+    row[2 * lane + 1] = v1;
+    __syncthreads();
+    T s = T(0);
+#pragma unroll
+    for (int d = -2 * K; d <= 2 * K; ++d) s = fma(cg[d + 2 * K], row[min(max(2 * lane + d, 0), 127)], s);
+    __syncthreads();
+    return s;
+  };
+  auto emit = [&](int Y, T v) {
+    if (!out_lane) return;
+    const bool dir = xdir || Y == 0 || Y == a.n1c - 1;
+    buf_store<T>(dir ? T(0) : v, orr, xoff, src * (unsigned)Y);
+  };
+  T carry = T(0);
+  for (int c = cs; c < c1; ++c) {
+    T acc[K + 1];
+#pragma unroll
+    for (int i = 0; i <= K; ++i) acc[i] = T(0);
+#pragma unroll
+    for (int l = 0; l < 2 * K; ++l) {
+      const T sx = xrow(2 * K * c + l);
+#pragma unroll
+      for (int i = 0; i <= K; ++i) acc[i] = fma(a.z[i * ZW + l], sx, acc[i]);
+    }
+    acc[0] += carry;
+    if (c >= c0) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) emit(K * c + i, acc[i]);
+    }
+    carry = acc[K];
+  }
+  if (c1 == a.ncc) emit(a.n1c - 1, carry);  // the last coarse row (Dirichlet: zero)
+}
+
+// ---- prolongate-add u_f += P e_c ----
+//
+// One wavefront owns a strip of 64 fine output columns and walks a chunk of
+// coarse cell rows: the K + 1 coarse rows of a cell are contracted along x
+// from LDS (each fine column from the K + 1 coarse nodes of its coarse cell)
+// and interpolated into the cell's 2K fine rows, which are read, added to and
+// written once; the coarse vertex row is shared with the next cell.  Fine
+// Dirichlet rows and columns are left as they are.
+template <typename T, int K>
+__global__ void __launch_bounds__(64) stream2_prolong_kernel(const Tr2Args<T, K> a) {
+  constexpr int W = K + 1, S = 2 * K;
+  __shared__ T row[64];
+  const unsigned h = blockIdx.x;
+  const unsigned per = gridDim.x / kXcd;
+  const unsigned logical = (h % kXcd) * per + h / kXcd;
+  if (logical >= a.nblocks) return;
+  const int lane = threadIdx.x;
+  const int strip = (int)(logical % (unsigned)a.strips);
+  const int chunk = (int)(logical / (unsigned)a.strips);
+  const int c0 = chunk * a.cz, c1 = min(a.ncc, c0 + a.cz);
+  const int x = strip * 64 + lane;  // this lane's fine column
+  const bool xin = x > 0 && x < a.n1f - 1;
+  const int cx = min(x, a.n1f - 2) / S;  // its coarse cell
+  const int j = min(x, a.n1f - 2) - S * cx;  // its position in the cell (0..2K-1)
+  const int X0 = (strip * 64) / S * K;       // first coarse column the strip reads
+  const int XL = K * cx - X0;                // this lane's first coarse node, in the strip's coarse row
+  const __amdgpu_buffer_rsrc_t ir = make_rsrc(a.in, a.bytes_in);
+  const __amdgpu_buffer_rsrc_t orr = make_rsrc(a.out, a.bytes_out);
+  const unsigned srf = (unsigned)a.n1f * (unsigned)sizeof(T), src = (unsigned)a.n1c * (unsigned)sizeof(T);
+  const int Xl = X0 + lane;  // coarse column loaded by this lane
+  const bool cin = Xl < a.n1c;
+  const unsigned coff = (unsigned)(cin ? Xl : 0) * (unsigned)sizeof(T);
+  const unsigned xoff = (unsigned)(xin ? x : 0) * (unsigned)sizeof(T);
+  T pj[W];  // the lane's row of P inside its coarse cell
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    T v = T(0);
+#pragma unroll
+    for (int q = 0; q < S; ++q) v = (j == q) ? a.z[q * W + i] : v;
+    pj[i] = v;
+  }
+  auto xrow = [&](int Y) {
+    row[lane] = cin ? buf_load<T>(ir, coff, src * (unsigned)Y) : T(0);
+    __syncthreads();
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < W; ++i) s = fma(pj[i], row[min(max(XL + i, 0), 63)], s);
+    __syncthreads();
+    return s;
+  };
+  T ex[W];
+  ex[0] = xrow(K * c0);
+  for (int c = c0; c < c1; ++c) {
+#pragma unroll
+    for (int i = 1; i <= K; ++i) ex[i] = xrow(K * c + i);
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int y = S * c + q;
+      T v = T(0);
+#pragma unroll
+      for (int i = 0; i < W; ++i) v = fma(a.z[q * W + i], ex[i], v);
+      if (xin && y > 0) {
+        const T uf = buf_load<T>(orr, xoff, srf * (unsigned)y);
+        buf_store<T>(uf + v, orr, xoff, srf * (unsigned)y);
+      }
+    }
+    ex[0] = ex[K];
+  }
+}
+
 }  // namespace
 
 template <typename T, int K>
@@ -169,7 +340,65 @@ hipError_t launch_stream2_operator(const Stream2Launch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
-#define VPS_STREAM2(T, K) template hipError_t launch_stream2_operator<T, K>(const Stream2Launch&, hipStream_t);
+template <typename T, int K>
+hipError_t launch_stream2_restrict(const Stream2Launch& L, hipStream_t s) {
+  static_assert(sizeof(Tr2Args<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
+  constexpr int WO = 64 - 2 * K;
+  Tr2Args<T, K> a;
+  a.in = (const T*)L.in;
+  a.out = (T*)L.out;
+  a.ncc = L.ncell;  // coarse cells
+  a.n1c = K * L.ncell + 1;
+  a.n1f = 2 * K * L.ncell + 1;
+  a.strips = (a.n1c + WO - 1) / WO;
+  const long long want = std::max(1LL, (long long)a.strips * a.ncc / 8192);
+  a.cz = (int)std::min<long long>(a.ncc, std::max<long long>(4, want));
+  const long long chunks = (a.ncc + a.cz - 1) / a.cz;
+  const unsigned long long nb = (unsigned long long)a.strips * chunks;
+  const unsigned long long bi = (unsigned long long)a.n1f * a.n1f * sizeof(T);
+  const unsigned long long bo = (unsigned long long)a.n1c * a.n1c * sizeof(T);
+  if (nb >= (1ull << 31) || bi >= (1ull << 32)) return hipErrorInvalidValue;
+  a.nblocks = (unsigned)nb;
+  a.bytes_in = (unsigned)bi;
+  a.bytes_out = (unsigned)bo;
+  for (int i = 0; i < K * (4 * K + 1); ++i) a.g[i] = (T)L.Mc[i];
+  for (int i = 0; i < (K + 1) * (2 * K + 1); ++i) a.z[i] = (T)L.Kc[i];
+  const unsigned grid = (a.nblocks + kXcd - 1) / kXcd * kXcd;
+  stream2_restrict_kernel<T, K><<<grid, 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T, int K>
+hipError_t launch_stream2_prolong(const Stream2Launch& L, hipStream_t s) {
+  static_assert(sizeof(Tr2Args<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
+  Tr2Args<T, K> a;
+  a.in = (const T*)L.in;
+  a.out = (T*)L.out;
+  a.ncc = L.ncell;
+  a.n1c = K * L.ncell + 1;
+  a.n1f = 2 * K * L.ncell + 1;
+  a.strips = (a.n1f + 63) / 64;
+  const long long want = std::max(1LL, (long long)a.strips * a.ncc / 8192);
+  a.cz = (int)std::min<long long>(a.ncc, std::max<long long>(4, want));
+  const long long chunks = (a.ncc + a.cz - 1) / a.cz;
+  const unsigned long long nb = (unsigned long long)a.strips * chunks;
+  const unsigned long long bi = (unsigned long long)a.n1c * a.n1c * sizeof(T);
+  const unsigned long long bo = (unsigned long long)a.n1f * a.n1f * sizeof(T);
+  if (nb >= (1ull << 31) || bo >= (1ull << 32)) return hipErrorInvalidValue;
+  a.nblocks = (unsigned)nb;
+  a.bytes_in = (unsigned)bi;
+  a.bytes_out = (unsigned)bo;
+  for (int i = 0; i < K * (4 * K + 1); ++i) a.g[i] = T(0);
+  for (int i = 0; i < 2 * K * (K + 1); ++i) a.z[i] = (T)L.Mc[i];
+  const unsigned grid = (a.nblocks + kXcd - 1) / kXcd * kXcd;
+  stream2_prolong_kernel<T, K><<<grid, 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+#define VPS_STREAM2(T, K)                                                             \
+  template hipError_t launch_stream2_operator<T, K>(const Stream2Launch&, hipStream_t); \
+  template hipError_t launch_stream2_restrict<T, K>(const Stream2Launch&, hipStream_t); \
+  template hipError_t launch_stream2_prolong<T, K>(const Stream2Launch&, hipStream_t);
 VPS_STREAM2(double, 1)
 VPS_STREAM2(double, 2)
 VPS_STREAM2(double, 3)

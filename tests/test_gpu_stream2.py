@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import vps_inputs as vi
-from oracle import assemble, fe
+from oracle import assemble, fe, transfer
 from tests.gpu_util import dev, host, rel, say
 
 pytestmark = pytest.mark.gpu
@@ -92,3 +92,42 @@ def test_operator_full_size_sampled_2d(vps, k):
         w = np.outer(M1[y, ys], K1[x, xs]) + np.outer(K1[y, ys], M1[x, xs])
         want = float((w * blk).sum())
         assert abs(got[y, x] - want) <= 1e-13 * float(np.abs(w * blk).sum()) + 1e-300, (x, y)
+
+
+TRANSFER_CASES = [(1, 80), (2, 40), (3, 25), (4, 18), (5, 15), (2, 5)]
+
+
+@pytest.mark.parametrize("k,Nc", TRANSFER_CASES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_restrict_2d(vps, k, Nc, dtype):
+    import torch
+    say("2D stream restrict", k, Nc, dtype)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    rf = vi.seeded_vector(2, k, 2 * Nc, 45)
+    if dtype == "f32":
+        rf = rf.astype(np.float32).astype(np.float64)
+    want = transfer.restrict_kron(2, k, Nc, rf)
+    tol = 1e-13 if dtype == "f64" else 2e-6
+    with vps.Context(2, k, 2 * Nc, 2, vcycle_dtype=dtype, stream_min_cells=1) as ctx:
+        rc = torch.full((want.size,), 3.0, dtype=tdt, device="cuda")
+        ctx.restrict(1, dev(rf, tdt), rc)
+        assert rel(host(rc), want) <= tol
+
+
+@pytest.mark.parametrize("k,Nc", TRANSFER_CASES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_prolong_2d(vps, k, Nc, dtype):
+    import torch
+    say("2D stream prolong", k, Nc, dtype)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    ec = vi.seeded_vector(2, k, Nc, 46)
+    uf = vi.seeded_vector(2, k, 2 * Nc, 47)
+    if dtype == "f32":
+        ec = ec.astype(np.float32).astype(np.float64)
+        uf = uf.astype(np.float32).astype(np.float64)
+    want = uf + transfer.prolong_kron(2, k, Nc, ec)
+    tol = 1e-13 if dtype == "f64" else 2e-6
+    with vps.Context(2, k, 2 * Nc, 2, vcycle_dtype=dtype, stream_min_cells=1) as ctx:
+        u = dev(uf, tdt)
+        ctx.prolongate_add(1, dev(ec, tdt), u)
+        assert rel(host(u), want) <= tol
