@@ -20,7 +20,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import subprocess
@@ -33,15 +32,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "patch_sweep_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_02100_amd", "csrc", f) for f in ("patch_wave.h",)]
 
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+from paper_2407_02100_amd.traffic_probe import kernel_source_hash  # noqa: E402  (hash of the smoother sources)
 
 
 def color_counts(dim: int, k: int, n: int, vlo: int = 1, vhi: int | None = None):
@@ -207,9 +199,10 @@ def run_sweep_protocol(torch, vps, vi, name="poisson3d_q4_n128"):
         nbytes = sweep_bytes(dim, k, N, word, bl)
         out["combined_batched"] = {"batch_layers": bl, "sweep_ms": ms, "dof_per_s": n / (ms * 1e-3),
                                    "alg_bytes_per_sweep": nbytes, "alg_gbs": nbytes / (ms * 1e-3) / 1e9}
+    # (on the one-patch-per-wave kernel, the one that visits patches in any of these orders)
     out["patch_order_sweep_ms"] = {}
     for order, label in orders.items():
-        with vps.Context(dim, k, N, 1, vcycle_dtype=w["vcycle"], patch_order=order) as ctx:
+        with vps.Context(dim, k, N, 1, vcycle_dtype=w["vcycle"], patch_order=order, patches_per_wave=1) as ctx:
             for _ in range(3):
                 ctx.smooth(0, u, b, sweeps=1)
             out["patch_order_sweep_ms"][label] = _median_ms(torch, lambda: ctx.smooth(0, u, b, sweeps=1))
@@ -454,7 +447,7 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "patch_wave3_kernel (one color of one batch of the smoother, finest level)",
+                     "kernel": "patch_row3_kernel (one color of one batch of the smoother, finest level)",
                      "avg_launch_us": per_launch_s * 1e6, "bytes_per_launch": bytes_sweep / lps,
                      "launches_per_sweep": lps,
                      "measured_copy_gbs": copy_gbs},

@@ -398,13 +398,18 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   P.coef = coef;
   P.pb = c->cfg.patches_per_block;  // 0: the launcher chooses
   P.order = c->cfg.patch_order;
-  // automatic: pairs on levels of at least 32 cells per direction (below, a color has
-  // too few patches to fill the chip twice over and one patch per wave finishes
-  // sooner), except FP32 at degree 4 (there one patch per wave is as fast on whole
-  // colors and faster in slab batches, measured at 513^3)
-  const bool pair_auto = L.ncell >= 32 && !(t == VPS_F32 && c->cfg.degree == 4);
-  P.ppw = pair_kernel_applies(c->cfg) && (c->cfg.patches_per_wave == 2 || (c->cfg.patches_per_wave == 0 && pair_auto))
-              ? 2 : 1;
+  // automatic (sweeps measured per degree, precision and level size): a row of
+  // patches per wave at degree 2 from 32 cells per direction and at degree 3 from
+  // 64, at degree 4 in FP32 from 64 (in FP64 its registers leave one wave per SIMD
+  // and pairs stay faster); otherwise pairs from 32 cells except FP32 at degree 4;
+  // one patch per wave on smaller levels (too few groups to fill the chip)
+  const int deg = c->cfg.degree;
+  const bool row_auto = (deg == 2 && L.ncell >= 32) || (deg == 3 && L.ncell >= 64) ||
+                        (deg == 4 && t == VPS_F32 && L.ncell >= 64);
+  const bool pair_auto = L.ncell >= 32 && !(t == VPS_F32 && deg == 4);
+  int ppw = c->cfg.patches_per_wave;
+  if (ppw == 0) ppw = row_auto ? 3 : (pair_auto ? 2 : 1);
+  P.ppw = pair_kernel_applies(c->cfg) ? ppw : 1;
   P.row2 = c->cfg.wave_rows_2d;
   P.vlo = vlo;
   P.vhi = vhi;
@@ -777,8 +782,8 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.patch_order < 0 || C.patch_order > 3) return VPS_E_ARG;
   if (C.batch_layers < 0) return VPS_E_ARG;
   if (C.batch_layers > 0 && C.algorithm != VPS_ALG_COMBINED) return VPS_E_UNSUPPORTED;
-  if (C.patches_per_wave < 0 || C.patches_per_wave > 2) return VPS_E_ARG;
-  if (C.patches_per_wave == 2 && !pair_kernel_applies(C)) return VPS_E_UNSUPPORTED;
+  if (C.patches_per_wave < 0 || C.patches_per_wave > 3) return VPS_E_ARG;
+  if (C.patches_per_wave >= 2 && !pair_kernel_applies(C)) return VPS_E_UNSUPPORTED;
   if (C.vcycle_graph != 0 && C.vcycle_graph != 1) return VPS_E_ARG;
   if (C.wave_rows_2d < 0 || C.wave_rows_2d > 2) return VPS_E_ARG;
   if (C.wave_rows_2d == 1 && (C.dim != 2 || C.coef != VPS_COEF_CONST || C.degree < 2 || C.patches_per_block != 0))

@@ -6,6 +6,7 @@
 #include "patch_wave.h"
 #include "patch_pair.h"
 #include "patch_row2.h"
+#include "patch_row3.h"
 #include "patch_big.h"
 #include "patch_solve.h"
 #include "launch.h"
@@ -138,6 +139,34 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
       static_assert(sizeof(PairArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
       const unsigned long long vbytes = (unsigned long long)a.n1 * a.n1 * a.n1 * sizeof(T);
       if (vbytes >= (1ull << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
+      if (L.ppw == 3) {
+        if (L.order != 0) return hipErrorInvalidValue;  // rows are visited in lexicographic order only
+        static_assert(sizeof(Row3Args<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
+        using R = Row3Shape<K>;
+        Row3Args<T, K> w;
+        w.u = a.u;
+        w.b = a.b;
+        w.n1 = a.n1;
+        for (int e = 0; e < 3; ++e) {
+          w.v0[e] = a.v0[e];
+          w.np[e] = a.np[e];
+        }
+        w.ngx = (a.np[0] + R::G - 1) / R::G;
+        const unsigned long long ng = (unsigned long long)w.ngx * (unsigned)a.np[1] * (unsigned)a.np[2];
+        // the group decomposition divides numbers below ngroups by ngx and np[1]
+        if (ng * (unsigned)w.ngx >= (1ull << 32) || ng * (unsigned)a.np[1] >= (1ull << 32)) return hipErrorInvalidValue;
+        w.ngroups = (unsigned)ng;
+        w.vec_bytes = (unsigned)vbytes;
+        w.magic_g = magic_of((unsigned)w.ngx);
+        w.magic_y = magic_of((unsigned)a.np[1]);
+        if (!make_band<T, K>(L.M[0], L.Kst[0], &w.band)) return hipErrorInvalidValue;
+        for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
+        for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
+        for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];
+        const unsigned grid = (w.ngroups + kXcd - 1) / kXcd * kXcd;  // a multiple of the XCD count
+        patch_row3_kernel<T, K><<<grid, 64, 0, s>>>(w);
+        return hipGetLastError();
+      }
       if (L.ppw == 2) {
         if (L.order != 0) return hipErrorInvalidValue;  // pairs are visited in lexicographic order only
         PairArgs<T, K> w;

@@ -1,0 +1,277 @@
+// Patch smoother kernel for 3D, constant coefficient: a row of x-adjacent
+// patches of one color per wavefront, lanes on node columns.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "patch_wave.h"
+
+namespace vps {
+
+// ---------------------------------------------------------------------------
+// Same update as patch_wave3_kernel (exact local solve from the closure with
+// the interior values taken as zero, fast diagonalisation in even/odd form).
+// Same-color patches 2 vertices apart along x share a closure face, so G of
+// them side by side span G*2K + 1 node columns.  One lane per column loads
+// every x row of the G closures as one contiguous run (up to 61 values):
+// a closure row that crosses the patches' interiors carries only the face
+// columns, the others the whole run.  Per patch this touches about a third of
+// the cache lines of the one-patch kernel, whose short rows 2 KiB apart bind
+// it to the per-CU vector-memory path.
+//
+// Stages of the wave that owns G patches, for each interior node plane oz
+// of the patches in turn:
+//   A. lanes = closure columns: z then y contraction of the lane's column
+//      (held in registers) into the two x-line inputs of the residual,
+//      F_M = (M_y M_z) u and F_E = (K_y M_z + M_y K_z) u, and the right-hand
+//      side rows of the plane, into LDS;
+//   B. lanes = (patch, oy): x contraction of the row from LDS, local residual,
+//      T^T along x, kept in registers;
+// then, with every plane done,
+//   C. T^T along z in registers; LDS transpose to lanes (patch, mx): T^T
+//      along y, 1/Lambda, T along y, T along z, all in registers;
+//   D. LDS transpose to lanes (patch, interior column): T along x, one output
+//      per lane, and the store of the new interior as x rows.
+
+template <int K>
+struct Row3Shape {
+  static constexpr int P = 2 * K + 1, Q = 2 * K - 1, S = 2 * K;
+  static constexpr int G = 63 / S;     // patches per wave
+  static constexpr int C = G * S + 1;  // closure columns of the G patches
+  static constexpr int GQ = G * Q;     // interior columns (and x rows) of the G patches
+  static constexpr int PLANE = 3 * Q * C;          // LDS of stages A-B: F_M, F_E, rhs rows of one plane
+  static constexpr int CUBE = G * Q * Q * Q;       // LDS of stages C-D: the G interiors
+  static constexpr int LDS = PLANE > CUBE ? PLANE : CUBE;
+  static_assert(C <= 64 && GQ <= 64, "a row of patches must fit one wave");
+};
+
+template <typename T, int K>
+struct Row3Args {
+  T* __restrict__ u;
+  const T* __restrict__ b;
+  int n1;
+  int v0[3];
+  int np[3];
+  int ngx;             // groups of G patches per color row: ceil(np[0] / G)
+  unsigned ngroups;    // ngx * np[1] * np[2]
+  unsigned vec_bytes;  // bytes of one level vector (< 2^32)
+  unsigned magic_g, magic_y;  // magic_of(ngx), magic_of(np[1]) (see div_magic)
+  PatchBand<T, K> band;  // interior rows of the 2-cell patch mass and stiffness matrices
+  WaveFdm<T, K> f;
+  T lam[2 * K - 1];  // 1D generalized eigenvalues in the internal mode order
+};
+
+template <typename T, int K>
+__global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) {
+  using R = Row3Shape<K>;
+  constexpr int P = R::P, Q = R::Q, S = R::S, G = R::G, C = R::C, GQ = R::GQ, M = K - 1;
+  __shared__ T L[R::LDS];
+  T* FM = L;              // [oy][column] of the current plane
+  T* FE = L + Q * C;      // [oy][column]
+  T* BB = L + 2 * Q * C;  // [oy][column]: right-hand side of the current plane
+  T* W = L;               // stages C-D: [patch][.][.][.]
+
+  const unsigned h = blockIdx.x;
+  const unsigned per = gridDim.x / kXcd;
+  const unsigned g = (h % kXcd) * per + h / kXcd;  // one contiguous slab of groups per XCD
+  if (g >= a.ngroups) return;
+  const int lane = threadIdx.x;
+  const unsigned ngx = (unsigned)a.ngx, npy = (unsigned)a.np[1];
+  const unsigned q1 = div_magic(g, ngx, a.magic_g);
+  const unsigned q2 = div_magic(q1, npy, a.magic_y);
+  const int px0 = G * (int)(g - q1 * ngx);
+  const int py = (int)(q1 - q2 * npy);
+  const int pz = (int)q2;
+  const int nact = min(G, a.np[0] - px0);  // patches of the group that exist
+  const int cmax = nact * S;               // last closure column that exists
+  const unsigned n1 = (unsigned)a.n1;
+  const size_t n2 = (size_t)n1 * n1;
+  const size_t base = (size_t)(K * (a.v0[0] + 2 * px0 - 1)) + (size_t)n1 * (size_t)(K * (a.v0[1] + 2 * py - 1)) +
+                      n2 * (size_t)(K * (a.v0[2] + 2 * pz - 1));
+  const __amdgpu_buffer_rsrc_t ur = make_rsrc(a.u, a.vec_bytes);
+  const __amdgpu_buffer_rsrc_t br = make_rsrc(a.b, a.vec_bytes);
+  const unsigned sbase = (unsigned)(base * sizeof(T));  // group origin, bytes
+  const unsigned srow = n1 * (unsigned)sizeof(T);
+  const unsigned splane = (unsigned)(n2 * sizeof(T));
+
+  // ---- closure rows of u, issued before any arithmetic (lanes past the
+  //      group repeat its last column; rows across the interiors carry only
+  //      the face columns, the interior values count as zero) ----
+  const unsigned offc = (unsigned)min(lane, cmax) * (unsigned)sizeof(T);
+  const bool face = (lane % S) == 0 && lane <= cmax;
+  T uc[P][P];  // [z][y] of the lane's column
+#pragma unroll
+  for (int z = 0; z < P; ++z)
+#pragma unroll
+    for (int y = 0; y < P; ++y) {
+      if (y == 0 || y == P - 1 || z == 0 || z == P - 1) uc[z][y] = buf_load<T>(ur, offc, sbase + splane * z + srow * y);
+      else uc[z][y] = face ? buf_load<T>(ur, offc, sbase + splane * z + srow * y) : T(0);
+    }
+  T bnext[Q];  // right-hand side rows of the next plane (lanes = columns)
+#pragma unroll
+  for (int y = 0; y < Q; ++y) bnext[y] = buf_load<T>(br, offc, sbase + splane + srow * (y + 1));
+
+  const int l2 = min(lane, GQ - 1);
+  const int pp = l2 / Q, ll = l2 % Q;  // (patch, line) of stages B-D
+  const int c0 = pp * S;               // the patch's first closure column
+  T mr[Q][Q];                          // stage B output of lane (pp, oy = ll): [oz][mx]
+
+#pragma unroll
+  for (int oz = 0; oz < Q; ++oz) {
+    const int jz = oz + 1;
+    T bcur[Q];
+#pragma unroll
+    for (int y = 0; y < Q; ++y) bcur[y] = bnext[y];
+    if (oz + 1 < Q) {
+#pragma unroll
+      for (int y = 0; y < Q; ++y) bnext[y] = buf_load<T>(br, offc, sbase + splane * (oz + 2) + srow * (y + 1));
+    }
+    // ---- A. lanes = columns: z then y contraction of plane oz ----
+    if (lane < C) {
+      T zm[P], zk[P];
+#pragma unroll
+      for (int y = 0; y < P; ++y) {
+        T sm = T(0), sk = T(0);
+#pragma unroll
+        for (int z = 0; z < P; ++z) {
+          if (z < band_lo(jz, K) || z > band_hi(jz, K)) continue;
+          sm = fma(band_m(a.band, jz, z), uc[z][y], sm);
+          sk = fma(band_k(a.band, jz, z), uc[z][y], sk);
+        }
+        zm[y] = sm;
+        zk[y] = sk;
+      }
+#pragma unroll
+      for (int oy = 0; oy < Q; ++oy) {
+        const int jy = oy + 1;
+        T fm = T(0), fe = T(0);
+#pragma unroll
+        for (int y = 0; y < P; ++y) {
+          if (y < band_lo(jy, K) || y > band_hi(jy, K)) continue;
+          fm = fma(band_m(a.band, jy, y), zm[y], fm);
+          fe = fma(band_k(a.band, jy, y), zm[y], fe);
+          fe = fma(band_m(a.band, jy, y), zk[y], fe);
+        }
+        FM[oy * C + lane] = fm;
+        FE[oy * C + lane] = fe;
+        BB[oy * C + lane] = bcur[oy];
+      }
+    }
+    __syncthreads();
+    // ---- B. lanes = (patch, oy): x contraction, local residual, T^T along x ----
+    if (lane < GQ) {
+      const int oy = ll;
+      T fm[P], fe[P], r[Q];
+#pragma unroll
+      for (int x = 0; x < P; ++x) {
+        fm[x] = FM[oy * C + c0 + x];
+        fe[x] = FE[oy * C + c0 + x];
+      }
+#pragma unroll
+      for (int ox = 0; ox < Q; ++ox) {
+        const int jx = ox + 1;
+        T s = T(0);
+#pragma unroll
+        for (int x = 0; x < P; ++x) {
+          if (x < band_lo(jx, K) || x > band_hi(jx, K)) continue;
+          s = fma(band_k(a.band, jx, x), fm[x], s);
+          s = fma(band_m(a.band, jx, x), fe[x], s);
+        }
+        r[ox] = BB[oy * C + c0 + 1 + ox] - s;
+      }
+      fdm_forward<T, K>(a.f, r, mr[oz]);
+    }
+    __syncthreads();  // the next plane overwrites FM, FE, BB
+  }
+
+  // ---- C. T^T along z (registers), then lanes (patch, mx) ----
+  if (lane < GQ) {
+    const int oy = ll;
+#pragma unroll
+    for (int mx = 0; mx < Q; ++mx) {
+      T v[Q], c[Q];
+#pragma unroll
+      for (int oz = 0; oz < Q; ++oz) v[oz] = mr[oz][mx];
+      fdm_forward<T, K>(a.f, v, c);
+#pragma unroll
+      for (int mz = 0; mz < Q; ++mz) W[((pp * Q + mx) * Q + mz) * Q + oy] = c[mz];
+    }
+  }
+  __syncthreads();
+  T e[Q][Q];  // lane (pp, mx = ll): [mz][y], then [z][y]
+  if (lane < GQ) {
+    const int mx = ll;
+    T lmx = a.lam[0];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) lmx = (mx == q) ? a.lam[q] : lmx;
+#pragma unroll
+    for (int mz = 0; mz < Q; ++mz) {
+      T v[Q], c[Q];
+#pragma unroll
+      for (int oy = 0; oy < Q; ++oy) v[oy] = W[((pp * Q + mx) * Q + mz) * Q + oy];
+      fdm_forward<T, K>(a.f, v, c);  // T^T along y
+      const T s2 = lmx + a.lam[mz];
+#pragma unroll
+      for (int my = 0; my < Q; ++my) {
+        if constexpr (sizeof(T) == 4) c[my] *= __builtin_amdgcn_rcpf(s2 + a.lam[my]);
+        else c[my] /= (s2 + a.lam[my]);
+      }
+      fdm_backward<T, K>(a.f, c, e[mz]);  // T along y
+    }
+#pragma unroll
+    for (int y = 0; y < Q; ++y) {  // T along z
+      T v[Q], d[Q];
+#pragma unroll
+      for (int mz = 0; mz < Q; ++mz) v[mz] = e[mz][y];
+      fdm_backward<T, K>(a.f, v, d);
+#pragma unroll
+      for (int z = 0; z < Q; ++z) e[z][y] = d[z];
+    }
+  }
+  __syncthreads();  // every lane has read W
+  if (lane < GQ) {
+    const int mx = ll;
+#pragma unroll
+    for (int z = 0; z < Q; ++z)
+#pragma unroll
+      for (int y = 0; y < Q; ++y) W[((pp * Q + z) * Q + y) * Q + mx] = e[z][y];
+  }
+  __syncthreads();
+
+  // ---- D. lanes = (patch, interior column x): T along x, store the x rows ----
+  if (lane < GQ && pp < nact) {
+    const int x = ll;
+    const int i = x < M ? x : (x > M ? Q - 1 - x : M);  // folded index of x
+    const T sgn = x < M ? T(1) : (x > M ? T(-1) : T(0));
+    T te[K], to[K - 1];  // the row of Te and To that output x needs
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      T t = a.f.Te[j];
+#pragma unroll
+      for (int ii = 1; ii < K; ++ii) t = (i == ii) ? a.f.Te[ii * K + j] : t;
+      te[j] = t;
+    }
+#pragma unroll
+    for (int j = 0; j < K - 1; ++j) {
+      T t = a.f.To[j];
+#pragma unroll
+      for (int ii = 1; ii < K - 1; ++ii) t = (i == ii) ? a.f.To[ii * (K - 1) + j] : t;
+      to[j] = t;
+    }
+    const unsigned off2 = (unsigned)(c0 + 1 + x) * (unsigned)sizeof(T);
+#pragma unroll
+    for (int z = 0; z < Q; ++z)
+#pragma unroll
+      for (int y = 0; y < Q; ++y) {
+        const T* w = W + ((pp * Q + z) * Q + y) * Q;
+        T se = T(0), so = T(0);
+#pragma unroll
+        for (int j = 0; j < K; ++j) se = fma(te[j], w[j], se);
+#pragma unroll
+        for (int j = 0; j < K - 1; ++j) so = fma(to[j], w[K + j], so);
+        buf_store<T>(fma(sgn, so, se), ur, off2, sbase + splane * (z + 1) + srow * (y + 1));
+      }
+  }
+}
+
+}  // namespace vps

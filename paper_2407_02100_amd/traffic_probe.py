@@ -32,7 +32,7 @@ COPY_BYTES = 512 * 1024 * 1024  # bytes read by the calibration copy (and writte
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("patch_wave.h",):
+    for f in ("patch_wave.h", "patch_row3.h"):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -72,8 +72,8 @@ def _read(path):
     return out
 
 
-SMOOTHER_KERNELS = ("patch_wave3_kernel", "patch_pair3_kernel", "patch_color_kernel", "patch_solve3_kernel",
-                    "stream3_kernel")
+SMOOTHER_KERNELS = ("patch_wave3_kernel", "patch_pair3_kernel", "patch_row3_kernel", "patch_color_kernel",
+                    "patch_solve3_kernel", "stream3_kernel")
 
 
 def summarize(fetch_csv: str, write_csv: str, dtype: str, workload: str = "poisson3d_q4_n128",
@@ -104,7 +104,8 @@ def summarize(fetch_csv: str, write_csv: str, dtype: str, workload: str = "poiss
            "kernels": kernels, "bytes_per_sweep": sweep, "calibration": scales,
            "note": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE per dispatch, each scaled by the value the "
                    "same counter reads for a plain copy of 512 MiB in the same process"}
-    main = kernels.get("patch_wave3_kernel") or kernels.get("patch_pair3_kernel") or kernels.get("patch_color_kernel")
+    main = (kernels.get("patch_row3_kernel") or kernels.get("patch_wave3_kernel") or kernels.get("patch_pair3_kernel")
+            or kernels.get("patch_color_kernel"))
     if main:
         doc["bytes_per_launch"] = main["fetch_bytes_per_launch"] + main["write_bytes_per_launch"]
     out_path = out_path or os.path.join(ROOT, "profiles", "patch_sweep_traffic.json")

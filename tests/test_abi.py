@@ -60,7 +60,7 @@ def test_status_strings(lib):
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, batch_layers=-1), -1),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, algorithm=1, batch_layers=2), -2),
     (dict(dim=3, degree=4, n_cells=204, n_levels=2), -2),  # 817^3 FP64 values exceed 32-bit byte offsets
-    (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=3), -1),
+    (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=4), -1),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, vcycle_graph=2), -1),
     (dict(dim=2, degree=2, n_cells=8, n_levels=2, wave_rows_2d=3), -1),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, wave_rows_2d=1), -2),   # row kernel: 2D only
@@ -72,6 +72,9 @@ def test_status_strings(lib):
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=2, patch_order=1), -2),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=2, algorithm=1), -2),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=2, patches_per_block=2), -2),
+    (dict(dim=2, degree=2, n_cells=8, n_levels=2, patches_per_wave=3), -2),   # rows of patches: 3D only
+    (dict(dim=3, degree=5, n_cells=8, n_levels=2, patches_per_wave=3), -2),   # rows of patches: degree 2..4
+    (dict(dim=3, degree=3, n_cells=8, n_levels=2, patches_per_wave=3, patch_order=3), -2),
 ])
 def test_create_rejects_invalid_configurations(lib, cfg, status):
     from paper_2407_02100_amd import vps

@@ -65,9 +65,10 @@ def _sample_vertices(n_cells, color, count, seed):
 
 
 @pytest.mark.parametrize("dtype,color", [("f32", 0), ("f32", 5), ("f64", 3)])
-@pytest.mark.parametrize("ppw", [1, 2])
+@pytest.mark.parametrize("ppw", [1, 2, 3])
 def test_color_on_sampled_patches_full_size(vps, dtype, color, ppw):
-    """One color launch at 513^3 against the oracle's exact local solve of sampled patches (1 or 2 patches per wave)."""
+    """One color launch at 513^3 against the oracle's exact local solve of sampled patches (one patch, two
+    patches or a row of seven per wave)."""
     import torch
     k, N = K5, N5
     say("full-size color", dtype, color, ppw)
