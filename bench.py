@@ -75,6 +75,23 @@ def sweep_bytes(dim: int, k: int, n: int, word: int, batch_layers: int = 0) -> i
                for clo, inner in color_counts(dim, k, n, lo, hi))
 
 
+def finest_smoother_kernel(dim: int, k: int, n_cells: int, vcycle: str, coef: str) -> str:
+    """The smoother kernel the library's automatic choice (vps_config.patches_per_wave = 0) runs on a level."""
+    if coef != "const":
+        return "patch_color_kernel"
+    if dim == 2:
+        return "patch_row2_kernel" if n_cells >= 64 and k >= 2 else "patch_color_kernel"
+    if k == 5:
+        return "patch_big3_kernel"
+    if k == 1:
+        return "patch_color_kernel"
+    if (k == 2 and n_cells >= 32) or (k == 3 and n_cells >= 64) or (k == 4 and vcycle == "f32" and n_cells >= 64):
+        return "patch_row3_kernel"
+    if n_cells >= 32 and not (vcycle == "f32" and k == 4):
+        return "patch_pair3_kernel"
+    return "patch_wave3_kernel"
+
+
 def launches_per_sweep(dim: int, n: int, batch_layers: int = 0) -> int:
     return sum(1 for lo, hi in batches(n, batch_layers) for clo, inner in color_counts(dim, 1, n, lo, hi) if inner)
 
@@ -190,7 +207,7 @@ def run_sweep_protocol(torch, vps, vi, name="poisson3d_q4_n128"):
     # dispatch-order study: the order in which the workgroups of a color visit its patches
     orders = {0: "lexicographic, one slab per XCD", 1: "lexicographic, round-robin over XCDs",
               2: "Morton curve, one slab per XCD", 3: "4x4x4 tiles, one slab per XCD"}
-    bl = w.get("batch_layers", 0)
+    bl = w.get("batch_layers", 0) or w.get("slab_layers", 0)
     if bl:
         with vps.Context(dim, k, N, 1, vcycle_dtype=w["vcycle"], batch_layers=bl) as ctx:
             for _ in range(3):
@@ -374,6 +391,7 @@ def main():
     ms_per_step = (t1 - t0) / args.steps * 1e3
 
     L = w["levels"] - 1
+    kname = finest_smoother_kernel(dim, k, N, w["vcycle"], w.get("coef", "const"))
     sweeps = tim["smooth_sweeps"][L]
     t_sm = tim["smooth_s"][L]
     value = n * sweeps / t_sm
@@ -430,7 +448,10 @@ def main():
                    "levels": w["levels"], "cycle": f"V({w['pre']},{w['post']})",
                    "vcycle_dtype": w["vcycle"], "outer": "FP64 flexible CG" if w["vcycle"] == "f32" else "FP64 PCG",
                    "rtol": 1e-10, "rhs": f"uniform [-1,1] on free nodes, seed {w['rhs_seed']}",
-                   "batch_layers": bl},
+                   "batch_layers": bl,
+                   "schedule": "one launch per color; a workgroup per batch of same-color patches"
+                               + (f" (a row of {63 // (2 * k)} x-adjacent patches on the finest level)"
+                                  if kname == "patch_row3_kernel" else "")},
         "solve": {"seconds": solve_s, "iterations": infos[-1]["iterations"],
                   "rel_residual_true": max(i["rel_residual_true"] for i in infos),
                   "vcycles_timed": tim["vcycles"]},
@@ -447,7 +468,7 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "patch_row3_kernel (one color of one batch of the smoother, finest level)",
+                     "kernel": f"{kname} (one color launch of the smoother, finest level)",
                      "avg_launch_us": per_launch_s * 1e6, "bytes_per_launch": bytes_sweep / lps,
                      "launches_per_sweep": lps,
                      "measured_copy_gbs": copy_gbs},
