@@ -85,7 +85,7 @@ def finest_smoother_kernel(dim: int, k: int, n_cells: int, vcycle: str, coef: st
         return "patch_big3_kernel"
     if k == 1:
         return "patch_color_kernel"
-    if (k == 2 and n_cells >= 32) or (k == 3 and n_cells >= 64) or (k == 4 and vcycle == "f32" and n_cells >= 64):
+    if (k == 2 and n_cells >= 32) or (k >= 3 and n_cells >= 64):
         return "patch_row3_kernel"
     if n_cells >= 32 and not (vcycle == "f32" and k == 4):
         return "patch_pair3_kernel"

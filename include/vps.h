@@ -118,10 +118,10 @@ typedef struct {
                             (their boundary columns are loaded together); 3 = a row of
                             floor(63 / 2k) x-adjacent patches (lanes on node columns,
                             closure rows loaded as contiguous runs); 0 = automatic
-                            (3 at degree 2 from 32 cells per direction, at degree 3
-                            from 64, at degree 4 in FP32 from 64; else 2 from 32
-                            cells except FP32 at degree 4; 1 otherwise).  Same update
-                            either way, different rounding order */
+                            (3 at degree 2 from 32 cells per direction, at degrees 3
+                            and 4 from 64; else 2 from 32 cells except FP32 at
+                            degree 4; 1 otherwise).  Same update either way,
+                            different rounding order */
   int vcycle_graph;      /* 1: the finest-level V-cycle of vps_vcycle and vps_solve is
                             captured once per (input, output) buffer pair into a HIP
                             graph on a stream of the library's own and replayed on the

@@ -399,13 +399,11 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   P.pb = c->cfg.patches_per_block;  // 0: the launcher chooses
   P.order = c->cfg.patch_order;
   // automatic (sweeps measured per degree, precision and level size): a row of
-  // patches per wave at degree 2 from 32 cells per direction and at degree 3 from
-  // 64, at degree 4 in FP32 from 64 (in FP64 its registers leave one wave per SIMD
-  // and pairs stay faster); otherwise pairs from 32 cells except FP32 at degree 4;
-  // one patch per wave on smaller levels (too few groups to fill the chip)
+  // patches per wave at degree 2 from 32 cells per direction, at degrees 3 and 4
+  // from 64; otherwise pairs from 32 cells except FP32 at degree 4; one patch per
+  // wave on smaller levels (too few groups to fill the chip)
   const int deg = c->cfg.degree;
-  const bool row_auto = (deg == 2 && L.ncell >= 32) || (deg == 3 && L.ncell >= 64) ||
-                        (deg == 4 && t == VPS_F32 && L.ncell >= 64);
+  const bool row_auto = (deg == 2 && L.ncell >= 32) || (deg >= 3 && L.ncell >= 64);
   const bool pair_auto = L.ncell >= 32 && !(t == VPS_F32 && deg == 4);
   int ppw = c->cfg.patches_per_wave;
   if (ppw == 0) ppw = row_auto ? 3 : (pair_auto ? 2 : 1);

@@ -13,20 +13,27 @@ namespace vps {
 // the interior values taken as zero, fast diagonalisation in even/odd form).
 // Same-color patches 2 vertices apart along x share a closure face, so G of
 // them side by side span G*2K + 1 node columns.  One lane per column loads
-// every x row of the G closures as one contiguous run (up to 61 values):
-// a closure row that crosses the patches' interiors carries only the face
-// columns, the others the whole run.  Per patch this touches about a third of
-// the cache lines of the one-patch kernel, whose short rows 2 KiB apart bind
-// it to the per-CU vector-memory path.
+// the closure rows of the G patches that lie on the rim of the (y, z)
+// cross-section (y or z on the closure boundary) as contiguous runs of up to
+// 61 values; the rows that cross the patches' interiors carry nonzero values
+// only in the G + 1 x-face columns: at K = 4 a prepass handles those apart
+// (which takes 45 registers off every lane), at K = 2, 3 the face lanes load
+// them with the rim and the other lanes hold zeros.  Per patch
+// this touches about a third of the cache lines of the one-patch kernel,
+// whose short rows 2 KiB apart bind it to the per-CU vector-memory path.
 //
-// Stages of the wave that owns G patches, for each interior node plane oz
-// of the patches in turn:
-//   A. lanes = closure columns: z then y contraction of the lane's column
-//      (held in registers) into the two x-line inputs of the residual,
-//      F_M = (M_y M_z) u and F_E = (K_y M_z + M_y K_z) u, and the right-hand
-//      side rows of the plane, into LDS;
-//   B. lanes = (patch, oy): x contraction of the row from LDS, local residual,
-//      T^T along x, kept in registers;
+// Stages of the wave that owns G patches:
+//   P. (K = 4) lanes = (x face, y): the interior (y, z) block of each x-face
+//      column, contracted along z in registers and along y after an LDS
+//      transpose, into its share of F_M and F_E (below), kept in LDS;
+// then for each interior node plane oz of the patches in turn:
+//   A. lanes = closure columns: z then y contraction of the rim of the
+//      lane's column (held in registers) into the two x-line inputs of the
+//      residual, F_M = (M_y M_z) u and F_E = (K_y M_z + M_y K_z) u, and the
+//      right-hand side rows of the plane, into LDS;
+//   B. lanes = (patch, oy): x contraction of the row from LDS (the face
+//      columns with their interior share added), local residual, T^T along
+//      x, kept in registers;
 // then, with every plane done,
 //   C. T^T along z in registers; LDS transpose to lanes (patch, mx): T^T
 //      along y, 1/Lambda, T along y, T along z, all in registers;
@@ -39,11 +46,54 @@ struct Row3Shape {
   static constexpr int G = 63 / S;     // patches per wave
   static constexpr int C = G * S + 1;  // closure columns of the G patches
   static constexpr int GQ = G * Q;     // interior columns (and x rows) of the G patches
+  static constexpr int F = G + 1;                 // x-face columns of the G patches
+  static constexpr bool FACE_PASS = K >= 4;        // stage P (measured faster at K = 4 only)
   static constexpr int PLANE = 3 * Q * C;          // LDS of stages A-B: F_M, F_E, rhs rows of one plane
+  static constexpr int FACE = FACE_PASS ? 2 * Q * Q * F : 0;  // LDS of stages P-B: the faces' interior share
   static constexpr int CUBE = G * Q * Q * Q;       // LDS of stages C-D: the G interiors
-  static constexpr int LDS = PLANE > CUBE ? PLANE : CUBE;
-  static_assert(C <= 64 && GQ <= 64, "a row of patches must fit one wave");
+  static constexpr int LDS = PLANE + FACE > CUBE ? PLANE + FACE : CUBE;
+  static_assert(C <= 64 && GQ <= 64 && F * Q <= 64, "a row of patches must fit one wave");
+  static_assert(FACE <= PLANE, "the prepass transpose (FACE values at the start) stays below the face buffer");
 };
+
+// The two cell matrices are symmetric: only their upper triangles travel as
+// kernel arguments (64 instead of 84 scalars for k = 4 with the FDM factors),
+// which keeps every constant of the kernel in scalar registers.
+template <typename T, int K>
+struct SymBand {
+  static constexpr int N = (K + 1) * (K + 2) / 2;
+  T m[N];  // upper triangle of the cell mass matrix, row by row
+  T k[N];  // ... of the cell stiffness matrix
+  T mvv, kvv;  // the middle vertex's diagonal: the sum over both cells
+};
+__host__ __device__ constexpr int sym_idx(int r, int c, int K) {
+  return r <= c ? r * (K + 1) - r * (r - 1) / 2 + (c - r) : c * (K + 1) - c * (c - 1) / 2 + (r - c);
+}
+// entry (j, z) of the band (interior node j, closure node z in j's cells), as band_at
+template <typename T, int K>
+__device__ inline T sym_at(const T (&c)[(K + 1) * (K + 2) / 2], T vv, int j, int z) {
+  if (j < K) return c[sym_idx(j, z, K)];
+  if (j > K) return c[sym_idx(j - K, z - K, K)];
+  if (z < K) return c[sym_idx(K, z, K)];
+  if (z > K) return c[sym_idx(0, z - K, K)];
+  return vv;
+}
+template <typename T, int K>
+__device__ inline T sym_m(const SymBand<T, K>& b, int j, int z) { return sym_at<T, K>(b.m, b.mvv, j, z); }
+template <typename T, int K>
+__device__ inline T sym_k(const SymBand<T, K>& b, int j, int z) { return sym_at<T, K>(b.k, b.kvv, j, z); }
+// from the full cell matrices (upper triangles kept)
+template <typename T, int K>
+inline void make_sym_band(const PatchBand<T, K>& b, SymBand<T, K>* s) {
+  constexpr int W = K + 1;
+  for (int r = 0; r < W; ++r)
+    for (int c = r; c < W; ++c) {
+      s->m[sym_idx(r, c, K)] = b.m[r * W + c];
+      s->k[sym_idx(r, c, K)] = b.k[r * W + c];
+    }
+  s->mvv = b.mvv;
+  s->kvv = b.kvv;
+}
 
 template <typename T, int K>
 struct Row3Args {
@@ -56,7 +106,7 @@ struct Row3Args {
   unsigned ngroups;    // ngx * np[1] * np[2]
   unsigned vec_bytes;  // bytes of one level vector (< 2^32)
   unsigned magic_g, magic_y;  // magic_of(ngx), magic_of(np[1]) (see div_magic)
-  PatchBand<T, K> band;  // interior rows of the 2-cell patch mass and stiffness matrices
+  SymBand<T, K> band;  // interior rows of the 2-cell patch mass and stiffness matrices
   WaveFdm<T, K> f;
   T lam[2 * K - 1];  // 1D generalized eigenvalues in the internal mode order
 };
@@ -65,10 +115,14 @@ template <typename T, int K>
 __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) {
   using R = Row3Shape<K>;
   constexpr int P = R::P, Q = R::Q, S = R::S, G = R::G, C = R::C, GQ = R::GQ, M = K - 1;
+  constexpr int F = R::F;
   __shared__ T L[R::LDS];
   T* FM = L;              // [oy][column] of the current plane
   T* FE = L + Q * C;      // [oy][column]
   T* BB = L + 2 * Q * C;  // [oy][column]: right-hand side of the current plane
+  T* DM = L + R::PLANE;   // [oz][oy][face]: interior share of F_M at the x-face columns
+  T* DE = DM + Q * Q * F; // [oz][oy][face]: ... of F_E
+  T* ZI = L;              // stage P: [t][face][oz][y] after the z contraction (below the face buffer)
   T* W = L;               // stages C-D: [patch][.][.][.]
 
   const unsigned h = blockIdx.x;
@@ -94,22 +148,76 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
   const unsigned srow = n1 * (unsigned)sizeof(T);
   const unsigned splane = (unsigned)(n2 * sizeof(T));
 
-  // ---- closure rows of u, issued before any arithmetic (lanes past the
-  //      group repeat its last column; rows across the interiors carry only
-  //      the face columns, the interior values count as zero) ----
+  // ---- every load of u, issued before any arithmetic: the rim rows of the
+  //      closures (lanes = columns; lanes past the group repeat its last
+  //      column) and the interior rows of the x-face columns (K = 4: lanes =
+  //      (face, y), faces past the group repeat its last face; else the face
+  //      lanes, the other lanes holding zeros) ----
+  constexpr bool FP = R::FACE_PASS;
   const unsigned offc = (unsigned)min(lane, cmax) * (unsigned)sizeof(T);
   const bool face = (lane % S) == 0 && lane <= cmax;
-  T uc[P][P];  // [z][y] of the lane's column
+  T uc[P][P];  // [z][y] of the lane's column (K = 4: rim only)
 #pragma unroll
   for (int z = 0; z < P; ++z)
 #pragma unroll
     for (int y = 0; y < P; ++y) {
       if (y == 0 || y == P - 1 || z == 0 || z == P - 1) uc[z][y] = buf_load<T>(ur, offc, sbase + splane * z + srow * y);
-      else uc[z][y] = face ? buf_load<T>(ur, offc, sbase + splane * z + srow * y) : T(0);
+      else if constexpr (!FP) uc[z][y] = face ? buf_load<T>(ur, offc, sbase + splane * z + srow * y) : T(0);
     }
+  const int lf = min(lane, F * Q - 1);
+  const int ff = lf / Q, fy = lf % Q;  // (face, interior row) of stage P
+  const unsigned offf = (unsigned)min(ff * S, cmax) * (unsigned)sizeof(T) + srow * (unsigned)(fy + 1);
+  T uf[Q];  // the face column's interior rows at y = fy + 1, along z
+  if constexpr (FP) {
+#pragma unroll
+    for (int z = 0; z < Q; ++z) uf[z] = buf_load<T>(ur, offf, sbase + splane * (z + 1));
+  }
   T bnext[Q];  // right-hand side rows of the next plane (lanes = columns)
 #pragma unroll
   for (int y = 0; y < Q; ++y) bnext[y] = buf_load<T>(br, offc, sbase + splane + srow * (y + 1));
+
+  // ---- P. the x faces' interior blocks: z contraction (lanes (face, y)),
+  //      y contraction (lanes (face, oz)) into DM, DE ----
+  if (FP && lane < F * Q) {
+#pragma unroll
+    for (int oz = 0; oz < Q; ++oz) {
+      const int jz = oz + 1;
+      T sm = T(0), sk = T(0);
+#pragma unroll
+      for (int z = 1; z < P - 1; ++z) {
+        if (z < band_lo(jz, K) || z > band_hi(jz, K)) continue;
+        sm = fma(sym_m(a.band, jz, z), uf[z - 1], sm);
+        sk = fma(sym_k(a.band, jz, z), uf[z - 1], sk);
+      }
+      ZI[(ff * Q + oz) * Q + fy] = sm;
+      ZI[((F + ff) * Q + oz) * Q + fy] = sk;
+    }
+  }
+  if constexpr (FP) __syncthreads();
+  if (FP && lane < F * Q) {
+    const int oz = fy;
+    T zm[Q], zk[Q];
+#pragma unroll
+    for (int y = 0; y < Q; ++y) {
+      zm[y] = ZI[(ff * Q + oz) * Q + y];
+      zk[y] = ZI[((F + ff) * Q + oz) * Q + y];
+    }
+#pragma unroll
+    for (int oy = 0; oy < Q; ++oy) {
+      const int jy = oy + 1;
+      T fm = T(0), fe = T(0);
+#pragma unroll
+      for (int y = 1; y < P - 1; ++y) {
+        if (y < band_lo(jy, K) || y > band_hi(jy, K)) continue;
+        fm = fma(sym_m(a.band, jy, y), zm[y - 1], fm);
+        fe = fma(sym_k(a.band, jy, y), zm[y - 1], fe);
+        fe = fma(sym_m(a.band, jy, y), zk[y - 1], fe);
+      }
+      DM[(oz * Q + oy) * F + ff] = fm;
+      DE[(oz * Q + oy) * F + ff] = fe;
+    }
+  }
+  if constexpr (FP) __syncthreads();  // the planes of stage A overwrite ZI
 
   const int l2 = min(lane, GQ - 1);
   const int pp = l2 / Q, ll = l2 % Q;  // (patch, line) of stages B-D
@@ -135,8 +243,9 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
 #pragma unroll
         for (int z = 0; z < P; ++z) {
           if (z < band_lo(jz, K) || z > band_hi(jz, K)) continue;
-          sm = fma(band_m(a.band, jz, z), uc[z][y], sm);
-          sk = fma(band_k(a.band, jz, z), uc[z][y], sk);
+          if (FP && y > 0 && y < P - 1 && z > 0 && z < P - 1) continue;  // off the rim (stage P)
+          sm = fma(sym_m(a.band, jz, z), uc[z][y], sm);
+          sk = fma(sym_k(a.band, jz, z), uc[z][y], sk);
         }
         zm[y] = sm;
         zk[y] = sk;
@@ -148,9 +257,9 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
 #pragma unroll
         for (int y = 0; y < P; ++y) {
           if (y < band_lo(jy, K) || y > band_hi(jy, K)) continue;
-          fm = fma(band_m(a.band, jy, y), zm[y], fm);
-          fe = fma(band_k(a.band, jy, y), zm[y], fe);
-          fe = fma(band_m(a.band, jy, y), zk[y], fe);
+          fm = fma(sym_m(a.band, jy, y), zm[y], fm);
+          fe = fma(sym_k(a.band, jy, y), zm[y], fe);
+          fe = fma(sym_m(a.band, jy, y), zk[y], fe);
         }
         FM[oy * C + lane] = fm;
         FE[oy * C + lane] = fe;
@@ -167,6 +276,12 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
         fm[x] = FM[oy * C + c0 + x];
         fe[x] = FE[oy * C + c0 + x];
       }
+      if constexpr (FP) {
+        fm[0] += DM[(oz * Q + oy) * F + pp];
+        fe[0] += DE[(oz * Q + oy) * F + pp];
+        fm[P - 1] += DM[(oz * Q + oy) * F + pp + 1];
+        fe[P - 1] += DE[(oz * Q + oy) * F + pp + 1];
+      }
 #pragma unroll
       for (int ox = 0; ox < Q; ++ox) {
         const int jx = ox + 1;
@@ -174,8 +289,8 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
 #pragma unroll
         for (int x = 0; x < P; ++x) {
           if (x < band_lo(jx, K) || x > band_hi(jx, K)) continue;
-          s = fma(band_k(a.band, jx, x), fm[x], s);
-          s = fma(band_m(a.band, jx, x), fe[x], s);
+          s = fma(sym_k(a.band, jx, x), fm[x], s);
+          s = fma(sym_m(a.band, jx, x), fe[x], s);
         }
         r[ox] = BB[oy * C + c0 + 1 + ox] - s;
       }

@@ -65,12 +65,12 @@ def test_pair_sweep_fp32(vps, k, N, reverse):
 
 
 @pytest.mark.parametrize("dtype,k,N,auto", [("f32", 4, 32, 1), ("f32", 3, 32, 2), ("f64", 4, 32, 2), ("f64", 2, 32, 3),
-                                          ("f64", 4, 16, 1), ("f32", 3, 9, 1), ("f32", 4, 64, 3), ("f64", 4, 64, 2),
+                                          ("f64", 4, 16, 1), ("f32", 3, 9, 1), ("f32", 4, 64, 3), ("f64", 4, 64, 3),
                                           ("f64", 3, 64, 3), ("f32", 2, 16, 1)])
 def test_automatic_patches_per_wave(vps, dtype, k, N, auto):
-    """patches_per_wave=0 takes a row of patches per wave at degree 2 from 32 cells, degree 3 from 64 and FP32
-    degree 4 from 64, else pairs from 32 cells except FP32 at degree 4: the same bits as that choice made
-    explicit; the other choices agree up to rounding."""
+    """patches_per_wave=0 takes a row of patches per wave at degree 2 from 32 cells and degrees 3 and 4 from
+    64, else pairs from 32 cells except FP32 at degree 4: the same bits as that choice made explicit; the
+    other choices agree up to rounding."""
     import torch
     say("automatic patches per wave", dtype, k, N)
     tdt = torch.float32 if dtype == "f32" else torch.float64
