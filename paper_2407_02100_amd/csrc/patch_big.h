@@ -33,9 +33,17 @@ struct BigArgs {
   unsigned npatch;
   unsigned vec_bytes;         // bytes of one level vector (< 2^32)
   unsigned magic_x, magic_y;  // magic_of(np[0]), magic_of(np[1]) (see div_magic)
-  PatchBand<T, K> band;       // interior rows of the 2-cell patch mass and stiffness matrices
+  SymBand<T, K> band;         // interior rows of the 2-cell patch mass and stiffness matrices
   WaveFdm<T, K> f;
   T lam[2 * K - 1];  // 1D generalized eigenvalues in the internal mode order
+};
+// The FDM factors and eigenvalues (50 scalars at K = 5) are read from LDS: with
+// the band coefficients they would not fit the scalar registers, and FP64
+// constants spilled to vector lanes cost two lane reads per use.
+template <typename T, int K>
+struct BigFdm {
+  WaveFdm<T, K> f;
+  T lam[2 * K - 1];
 };
 
 template <typename T, int K>
@@ -46,6 +54,7 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
   static_assert(NB <= 64, "the boundary columns must fit one wave");
   __shared__ T Z[2 * Q * P2];      // [t][oz][y][x] after the z contraction; later the FDM buffers
   __shared__ T AE[2 * Q * P * Q];  // [t][oz][y][ox] after the x contraction
+  __shared__ BigFdm<T, K> FS;
   T* W0 = Z;
   T* W1 = Z + Q3;
   static_assert(2 * Q3 <= 2 * Q * P2, "FDM buffers must fit in Z");
@@ -55,6 +64,14 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
   const unsigned logical = (h % kXcd) * per + h / kXcd;  // one contiguous slab of patches per XCD
   if (logical >= a.npatch) return;
   const int lane = threadIdx.x;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < K * K; ++q) FS.f.Te[q] = a.f.Te[q];
+#pragma unroll
+    for (int q = 0; q < (K - 1) * (K - 1); ++q) FS.f.To[q] = a.f.To[q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) FS.lam[q] = a.lam[q];
+  }
   const unsigned npx = (unsigned)a.np[0], npy = (unsigned)a.np[1];
   const unsigned qx = div_magic(logical, npx, a.magic_x);
   const unsigned qy = div_magic(qx, npy, a.magic_y);
@@ -104,8 +121,8 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
 #pragma unroll
       for (int z = 0; z < P; ++z) {
         if (z < band_lo(j, K) || z > band_hi(j, K)) continue;
-        zm = fma(band_m(a.band, j, z), vb[z], zm);
-        zk = fma(band_k(a.band, j, z), vb[z], zk);
+        zm = fma(sym_m(a.band, j, z), vb[z], zm);
+        zk = fma(sym_k(a.band, j, z), vb[z], zk);
       }
       Z[(0 * Q + o) * P2 + by * P + bx] = zm;
       Z[(1 * Q + o) * P2 + by * P + bx] = zk;
@@ -120,8 +137,8 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
       for (int o = 0; o < Q; ++o) {
         const int j = o + 1;
         T zm = T(0), zk = T(0);
-        if (band_lo(j, K) == 0) { zm = fma(band_m(a.band, j, 0), e0[s], zm); zk = fma(band_k(a.band, j, 0), e0[s], zk); }
-        if (band_hi(j, K) == P - 1) { zm = fma(band_m(a.band, j, P - 1), e1[s], zm); zk = fma(band_k(a.band, j, P - 1), e1[s], zk); }
+        if (band_lo(j, K) == 0) { zm = fma(sym_m(a.band, j, 0), e0[s], zm); zk = fma(sym_k(a.band, j, 0), e0[s], zk); }
+        if (band_hi(j, K) == P - 1) { zm = fma(sym_m(a.band, j, P - 1), e1[s], zm); zk = fma(sym_k(a.band, j, P - 1), e1[s], zk); }
         Z[(0 * Q + o) * P2 + col] = zm;
         Z[(1 * Q + o) * P2 + col] = zk;
       }
@@ -148,9 +165,9 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
 #pragma unroll
         for (int x = 0; x < P; ++x) {
           if (x < band_lo(j, K) || x > band_hi(j, K)) continue;
-          av = fma(band_m(a.band, j, x), zm[x], av);
-          ev = fma(band_k(a.band, j, x), zm[x], ev);
-          ev = fma(band_m(a.band, j, x), zk[x], ev);
+          av = fma(sym_m(a.band, j, x), zm[x], av);
+          ev = fma(sym_k(a.band, j, x), zm[x], ev);
+          ev = fma(sym_m(a.band, j, x), zk[x], ev);
         }
         AE[((0 * Q + oz) * P + y) * Q + o] = av;
         AE[((1 * Q + oz) * P + y) * Q + o] = ev;
@@ -179,12 +196,12 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
 #pragma unroll
         for (int y = 0; y < P; ++y) {
           if (y < band_lo(j, K) || y > band_hi(j, K)) continue;
-          acc = fma(band_k(a.band, j, y), av[y], acc);
-          acc = fma(band_m(a.band, j, y), ev[y], acc);
+          acc = fma(sym_k(a.band, j, y), av[y], acc);
+          acc = fma(sym_m(a.band, j, y), ev[y], acc);
         }
         r[o] = bv[s][o] - acc;
       }
-      fdm_forward<T, K>(a.f, r, m);
+      fdm_forward<T, K>(FS.f, r, m);
 #pragma unroll
       for (int q = 0; q < Q; ++q) W0[(oz * Q + q) * Q + ox] = m[q];
     }
@@ -199,7 +216,7 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
       T v[Q], m[Q];
 #pragma unroll
       for (int x = 0; x < Q; ++x) v[x] = W0[i * Q + x];
-      fdm_forward<T, K>(a.f, v, m);
+      fdm_forward<T, K>(FS.f, v, m);
 #pragma unroll
       for (int q = 0; q < Q; ++q) W1[i * Q + q] = m[q];
     }
@@ -215,18 +232,18 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
       T v[Q], c[Q];
 #pragma unroll
       for (int z = 0; z < Q; ++z) v[z] = W1[z * Q2 + i];
-      fdm_forward<T, K>(a.f, v, c);
-      T lmy = a.lam[0], lmx = a.lam[0];
+      fdm_forward<T, K>(FS.f, v, c);
+      T lmy = FS.lam[0], lmx = FS.lam[0];
 #pragma unroll
       for (int q = 1; q < Q; ++q) {
-        lmy = (my == q) ? a.lam[q] : lmy;
-        lmx = (mx == q) ? a.lam[q] : lmx;
+        lmy = (my == q) ? FS.lam[q] : lmy;
+        lmx = (mx == q) ? FS.lam[q] : lmx;
       }
       const T s2 = lmy + lmx;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        if constexpr (sizeof(T) == 4) W0[q * Q2 + i] = c[q] * __builtin_amdgcn_rcpf(s2 + a.lam[q]);
-        else W0[q * Q2 + i] = c[q] / (s2 + a.lam[q]);
+        if constexpr (sizeof(T) == 4) W0[q * Q2 + i] = c[q] * __builtin_amdgcn_rcpf(s2 + FS.lam[q]);
+        else W0[q * Q2 + i] = c[q] / (s2 + FS.lam[q]);
       }
     }
   }
@@ -240,7 +257,7 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
       T c[Q], d[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) c[q] = W0[i * Q + q];
-      fdm_backward<T, K>(a.f, c, d);
+      fdm_backward<T, K>(FS.f, c, d);
 #pragma unroll
       for (int x = 0; x < Q; ++x) W1[i * Q + x] = d[x];
     }
@@ -256,7 +273,7 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
       T c[Q], d[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) c[q] = W1[(mz * Q + q) * Q + x];
-      fdm_backward<T, K>(a.f, c, d);
+      fdm_backward<T, K>(FS.f, c, d);
 #pragma unroll
       for (int y = 0; y < Q; ++y) W0[(mz * Q + y) * Q + x] = d[y];
     }
@@ -271,7 +288,7 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
       T c[Q], d[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) c[q] = W0[q * Q2 + i];
-      fdm_backward<T, K>(a.f, c, d);
+      fdm_backward<T, K>(FS.f, c, d);
       const unsigned off = srow * (unsigned)(1 + i / Q) + (unsigned)(1 + i % Q) * (unsigned)sizeof(T);
 #pragma unroll
       for (int z = 0; z < Q; ++z) buf_store<T>(d[z], ur, off, sbase + splane * (z + 1));

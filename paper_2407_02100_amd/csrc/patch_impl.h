@@ -124,7 +124,9 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
       w.vec_bytes = (unsigned)vbytes;
       w.magic_x = magic_of((unsigned)a.np[0]);
       w.magic_y = magic_of((unsigned)a.np[1]);
-      if (!make_band<T, K>(L.M[0], L.Kst[0], &w.band)) return hipErrorInvalidValue;
+      PatchBand<T, K> band;
+      if (!make_band<T, K>(L.M[0], L.Kst[0], &band)) return hipErrorInvalidValue;
+      make_sym_band<T, K>(band, &w.band);
       for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
       for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
       for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];

@@ -73,6 +73,45 @@ __device__ inline T band_m(const PatchBand<T, K>& b, int j, int z) { return band
 template <typename T, int K>
 __device__ inline T band_k(const PatchBand<T, K>& b, int j, int z) { return band_at<T, K>(b.k, b.kvv, j, z); }
 
+// The two cell matrices are symmetric: only their upper triangles travel as
+// kernel arguments ((K+1)(K+2)/2 instead of (K+1)^2 scalars per matrix), so
+// that more of a kernel's constants stay in scalar registers.
+template <typename T, int K>
+struct SymBand {
+  static constexpr int N = (K + 1) * (K + 2) / 2;
+  T m[N];  // upper triangle of the cell mass matrix, row by row
+  T k[N];  // ... of the cell stiffness matrix
+  T mvv, kvv;  // the middle vertex's diagonal: the sum over both cells
+};
+__host__ __device__ constexpr int sym_idx(int r, int c, int K) {
+  return r <= c ? r * (K + 1) - r * (r - 1) / 2 + (c - r) : c * (K + 1) - c * (c - 1) / 2 + (r - c);
+}
+// entry (j, z) of the band (interior node j, closure node z in j's cells), as band_at
+template <typename T, int K>
+__device__ inline T sym_at(const T (&c)[(K + 1) * (K + 2) / 2], T vv, int j, int z) {
+  if (j < K) return c[sym_idx(j, z, K)];
+  if (j > K) return c[sym_idx(j - K, z - K, K)];
+  if (z < K) return c[sym_idx(K, z, K)];
+  if (z > K) return c[sym_idx(0, z - K, K)];
+  return vv;
+}
+template <typename T, int K>
+__device__ inline T sym_m(const SymBand<T, K>& b, int j, int z) { return sym_at<T, K>(b.m, b.mvv, j, z); }
+template <typename T, int K>
+__device__ inline T sym_k(const SymBand<T, K>& b, int j, int z) { return sym_at<T, K>(b.k, b.kvv, j, z); }
+// from the full cell matrices (upper triangles kept)
+template <typename T, int K>
+inline void make_sym_band(const PatchBand<T, K>& b, SymBand<T, K>* s) {
+  constexpr int W = K + 1;
+  for (int r = 0; r < W; ++r)
+    for (int c = r; c < W; ++c) {
+      s->m[sym_idx(r, c, K)] = b.m[r * W + c];
+      s->k[sym_idx(r, c, K)] = b.k[r * W + c];
+    }
+  s->mvv = b.mvv;
+  s->kvv = b.kvv;
+}
+
 // Fill a PatchBand from the interior rows (Q x P, row-major) of the 2-cell
 // patch matrices; false if they are not two copies of one cell matrix.
 template <typename T, int K>

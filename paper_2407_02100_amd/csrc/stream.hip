@@ -42,11 +42,24 @@ hipError_t go_stream(const StreamLaunch& L, hipStream_t s) {
     return hipErrorInvalidValue;
   a.nblocks = (unsigned)nb;
   constexpr int ZW = S::ZIN + 1;
-  for (int i = 0; i < S::PO * S::W; ++i) a.G0[i] = (T)L.G0[i];
-  for (int i = 0; i < S::ZO * ZW; ++i) a.Z0[i] = (T)L.Z0[i];
   if constexpr (S::OP) {
-    for (int i = 0; i < S::PO * S::W; ++i) a.G1[i] = (T)L.G1[i];
-    for (int i = 0; i < S::ZO * ZW; ++i) a.Z1[i] = (T)L.Z1[i];
+    // Z0, Z1: the cell mass and stiffness matrices ((K+1) x (K+1)); G0, G1: the period rows,
+    // whose vertex row (row 0) holds the diagonal summed over both cells at window position K
+    for (int r = 0; r <= K; ++r)
+      for (int c = r; c <= K; ++c) {
+        a.cm[cell_sym_idx(r, c, K)] = (T)L.Z0[r * ZW + c];
+        a.ck[cell_sym_idx(r, c, K)] = (T)L.Z1[r * ZW + c];
+      }
+    a.mvv = (T)L.G0[K];
+    a.kvv = (T)L.G1[K];
+    a.pt[0] = T(0);
+  } else {
+    // p[f][c], f = 0..K: the prolongation's period rows (G0, 2K x (K+1)), or the restriction's
+    // z table transposed (Z0[c][f] for fine planes f < 2K of a coarse cell)
+    for (int f = 0; f <= K; ++f)
+      for (int c = 0; c <= K; ++c)
+        a.pt[f * (K + 1) + c] = S::PR ? (T)L.G0[f * (K + 1) + c] : (T)L.Z0[c * ZW + f];
+    a.cm[0] = a.ck[0] = a.mvv = a.kvv = T(0);
   }
   const unsigned grid = (unsigned)((nb + kXcd - 1) / kXcd * kXcd);
   stream3_kernel<T, KIND, K><<<grid, kBlock, 0, s>>>(a);

@@ -64,9 +64,21 @@ struct StreamShape {
   static __host__ __device__ constexpr int hi(int j) { return OP ? 2 * K : PR ? K : 4 * K; }
 };
 
+// The operator's coefficients all come from the two symmetric cell matrices:
+// they travel as upper triangles (plus the vertex diagonal summed over its
+// two cells), 2 (K+1)(K+2)/2 + 2 scalars instead of 2 K (2K+1) + 2 (K+1)^2,
+// so that they stay in scalar registers.  The transfers' come from the 1D
+// interpolation of one coarse cell, p[f][c] (fine node f = 0..2K, coarse node
+// c = 0..K), whose rows past the middle mirror the first ones
+// (p[2K-f][K-c] = p[f][c]): (K+1)^2 scalars.
+__host__ __device__ constexpr int cell_sym_idx(int r, int c, int K) {
+  return r <= c ? r * (K + 1) - r * (r - 1) / 2 + (c - r) : c * (K + 1) - c * (c - 1) / 2 + (r - c);
+}
+
 template <typename T, int KIND, int K>
 struct StreamArgs {
   using S = StreamShape<KIND, K>;
+  static constexpr int NS = (K + 1) * (K + 2) / 2;
   const T* __restrict__ in;
   const T* __restrict__ b;  // operator only: out = b - A u if non-null
   T* __restrict__ out;
@@ -75,10 +87,38 @@ struct StreamArgs {
   int tiles_x, tiles_y;     // x-y tiles
   int cz;                   // z cells per chunk
   unsigned nblocks;         // tiles_x * tiles_y * chunks
-  T G0[S::PO * S::W];       // operator: mass period rows; transfers: restriction / prolongation rows
-  T G1[S::OP ? S::PO * S::W : 1];  // operator: stiffness period rows
-  T Z0[S::ZO * (S::ZIN + 1)];      // [out][in]: operator: cell mass; transfers: cell block
-  T Z1[S::OP ? S::ZO * (S::ZIN + 1) : 1];  // operator: cell stiffness
+  T pt[S::OP ? 1 : (K + 1) * (K + 1)];       // transfers: p[f][c] for f = 0..K
+  T cm[S::OP ? NS : 1], ck[S::OP ? NS : 1];  // operator: upper triangles of the cell mass / stiffness
+  T mvv, kvv;                                // operator: the vertex diagonal over both cells
+
+  __device__ T p1(int f, int c) const {
+    return f <= K ? pt[f * (K + 1) + c] : pt[(2 * K - f) * (K + 1) + (K - c)];
+  }
+
+  // period row j, window entry i of the x-y contraction: mass (t = 0) / stiffness (t = 1)
+  // for the operator (the vertex row j = 0 spans both cells, j > 0 the cell after it),
+  // the transfer rows otherwise
+  __device__ T g(int t, int j, int i) const {
+    if constexpr (S::OP) {
+      const T* c = t == 0 ? cm : ck;
+      if (j > 0) return c[cell_sym_idx(j, i - K, K)];
+      if (i < K) return c[cell_sym_idx(K, i, K)];
+      if (i > K) return c[cell_sym_idx(0, i - K, K)];
+      return t == 0 ? mvv : kvv;
+    } else if constexpr (S::PR) {
+      return p1(j, i);  // fine row j of the period, coarse node i
+    } else {
+      // coarse row j of the period (j = 0: the vertex between two coarse cells), fine node i of the window
+      if (j > 0) return p1(i - 2 * K, j);
+      return i <= 2 * K ? p1(i, K) : p1(i - 2 * K, 0);
+    }
+  }
+  // z fold: entry [out o][in l] of the cell matrix (operator) or cell block (transfers)
+  __device__ T z(int t, int o, int l) const {
+    if constexpr (S::OP) return (t == 0 ? cm : ck)[cell_sym_idx(o, l, K)];
+    else if constexpr (S::PR) return p1(o, l);  // fine plane o of the coarse cell from coarse plane l
+    else return p1(l, o);                       // coarse plane o from fine plane l of the coarse cell
+  }
 };
 
 template <typename T>
@@ -92,7 +132,6 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
   constexpr bool OP = S::OP;
   constexpr int PO = S::PO, PI = S::PI, W = S::W, TX = S::TX, TY = S::TY, NA = S::NA, ZIN = S::ZIN;
   constexpr int NOX = S::NOX, NIX = S::NIX, NIY = S::NIY, NIT = S::NIT, NPF = S::NPF;
-  constexpr int ZW = ZIN + 1;  // row length of the z tables
   __shared__ T U[NIY * NIX];
   __shared__ T XA[NA * NIY * NOX];
 
@@ -187,8 +226,8 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
         T s0 = T(0), s1 = T(0);
 #pragma unroll
         for (int i = S::lo(j); i <= S::hi(j); ++i) {
-          s0 = fma(a.G0[j * W + i], u[i], s0);
-          if constexpr (OP) s1 = fma(a.G1[j * W + i], u[i], s1);
+          s0 = fma(a.g(0, j, i), u[i], s0);
+          if constexpr (OP) s1 = fma(a.g(1, j, i), u[i], s1);
         }
         XA[yi * NOX + px * PO + j] = s0;
         if constexpr (OP) XA[NIY * NOX + yi * NOX + px * PO + j] = s1;
@@ -211,10 +250,10 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
         T s0 = T(0), s1 = T(0);
 #pragma unroll
         for (int i = S::lo(j); i <= S::hi(j); ++i) {
-          s0 = fma(a.G0[j * W + i], x0[i], s0);
+          s0 = fma(a.g(0, j, i), x0[i], s0);
           if constexpr (OP) {
-            s1 = fma(a.G0[j * W + i], x1[i], s1);
-            s1 = fma(a.G1[j * W + i], x0[i], s1);
+            s1 = fma(a.g(0, j, i), x1[i], s1);
+            s1 = fma(a.g(1, j, i), x0[i], s1);
           }
         }
         v0[m][j] = s0;
@@ -288,7 +327,7 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
           const T carry = acc[m][j][K];
 #pragma unroll
           for (int i = 0; i <= K; ++i)
-            acc[m][j][i] = fma(a.Z1[i * ZW + 0], pm[m][j], a.Z0[i * ZW + 0] * ps[m][j]);
+            acc[m][j][i] = fma(a.z(1, i, 0), pm[m][j], a.z(0, i, 0) * ps[m][j]);
           acc[m][j][0] += carry;
           if (resid) acc[m][j][0] -= cb[m][j];
         }
@@ -301,7 +340,7 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
           for (int j = 0; j < PO; ++j) {
 #pragma unroll
             for (int i = 0; i <= K; ++i)
-              acc[m][j][i] = fma(a.Z1[i * ZW + l], v0[m][j], fma(a.Z0[i * ZW + l], v1[m][j], acc[m][j][i]));
+              acc[m][j][i] = fma(a.z(1, i, l), v0[m][j], fma(a.z(0, i, l), v1[m][j], acc[m][j][i]));
             if (resid && l < K) acc[m][j][l] -= cb[m][j];
           }
       }
@@ -344,7 +383,7 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
 #pragma unroll
         for (int j = 0; j < PO; ++j)
 #pragma unroll
-          for (int q = 0; q < 2 * K; ++q) acc[m][j][q] = a.Z0[q * ZW + 0] * pv[m][j];
+          for (int q = 0; q < 2 * K; ++q) acc[m][j][q] = a.z(0, q, 0) * pv[m][j];
 #pragma unroll
       for (int l = 1; l <= K; ++l) {
         plane(K * c + l, plast);
@@ -353,7 +392,7 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
 #pragma unroll
           for (int j = 0; j < PO; ++j)
 #pragma unroll
-            for (int q = 0; q < 2 * K; ++q) acc[m][j][q] = fma(a.Z0[q * ZW + l], v0[m][j], acc[m][j][q]);
+            for (int q = 0; q < 2 * K; ++q) acc[m][j][q] = fma(a.z(0, q, l), v0[m][j], acc[m][j][q]);
       }
 #pragma unroll
       for (int m = 0; m < NIT; ++m)
@@ -400,11 +439,11 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
             if (l == 0) {
               const T carry = acc[m][j][K];
 #pragma unroll
-              for (int i = 0; i <= K; ++i) acc[m][j][i] = a.Z0[i * ZW + 0] * v0[m][j];
+              for (int i = 0; i <= K; ++i) acc[m][j][i] = a.z(0, i, 0) * v0[m][j];
               acc[m][j][0] += carry;
             } else {
 #pragma unroll
-              for (int i = 0; i <= K; ++i) acc[m][j][i] = fma(a.Z0[i * ZW + l], v0[m][j], acc[m][j][i]);
+              for (int i = 0; i <= K; ++i) acc[m][j][i] = fma(a.z(0, i, l), v0[m][j], acc[m][j][i]);
             }
           }
       }
