@@ -37,8 +37,8 @@ namespace vps {
 // then, with every plane done,
 //   C. T^T along z in registers; LDS transpose to lanes (patch, mx): T^T
 //      along y, 1/Lambda, T along y, T along z, all in registers;
-//   D. LDS transpose to lanes (patch, interior column): T along x, one output
-//      per lane, and the store of the new interior as x rows.
+//   D. lanes (patch, y): T along x on their x lines in LDS, in place; then
+//      lanes (patch, interior column) store the new interior as x rows.
 
 template <int K>
 struct Row3Shape {
@@ -314,39 +314,30 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
   }
   __syncthreads();
 
-  // ---- D. lanes = (patch, interior column x): T along x, store the x rows ----
+  // ---- D. lanes = (patch, y): T along x on the lane's own x lines, in place;
+  //      then lanes = (patch, interior column x): store the x rows ----
+  if (lane < GQ) {
+    const int y = ll;
+#pragma unroll
+    for (int z = 0; z < Q; ++z) {
+      T* w = W + ((pp * Q + z) * Q + y) * Q;
+      T c[Q], d[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) c[q] = w[q];
+      fdm_backward<T, K>(a.f, c, d);
+#pragma unroll
+      for (int x = 0; x < Q; ++x) w[x] = d[x];
+    }
+  }
+  __syncthreads();
   if (lane < GQ && pp < nact) {
     const int x = ll;
-    const int i = x < M ? x : (x > M ? Q - 1 - x : M);  // folded index of x
-    const T sgn = x < M ? T(1) : (x > M ? T(-1) : T(0));
-    T te[K], to[K - 1];  // the row of Te and To that output x needs
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      T t = a.f.Te[j];
-#pragma unroll
-      for (int ii = 1; ii < K; ++ii) t = (i == ii) ? a.f.Te[ii * K + j] : t;
-      te[j] = t;
-    }
-#pragma unroll
-    for (int j = 0; j < K - 1; ++j) {
-      T t = a.f.To[j];
-#pragma unroll
-      for (int ii = 1; ii < K - 1; ++ii) t = (i == ii) ? a.f.To[ii * (K - 1) + j] : t;
-      to[j] = t;
-    }
     const unsigned off2 = (unsigned)(c0 + 1 + x) * (unsigned)sizeof(T);
 #pragma unroll
     for (int z = 0; z < Q; ++z)
 #pragma unroll
-      for (int y = 0; y < Q; ++y) {
-        const T* w = W + ((pp * Q + z) * Q + y) * Q;
-        T se = T(0), so = T(0);
-#pragma unroll
-        for (int j = 0; j < K; ++j) se = fma(te[j], w[j], se);
-#pragma unroll
-        for (int j = 0; j < K - 1; ++j) so = fma(to[j], w[K + j], so);
-        buf_store<T>(fma(sgn, so, se), ur, off2, sbase + splane * (z + 1) + srow * (y + 1));
-      }
+      for (int y = 0; y < Q; ++y)
+        buf_store<T>(W[((pp * Q + z) * Q + y) * Q + x], ur, off2, sbase + splane * (z + 1) + srow * (y + 1));
   }
 }
 
