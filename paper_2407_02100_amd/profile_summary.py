@@ -1,6 +1,6 @@
 """Summarise a rocprofv3 kernel trace (rocpd SQLite output) per kernel and grid.
 
-Usage: python -m paper_2407_02100_amd.profile_summary RESULTS_DB [--top N]
+Usage: python -m paper_2407_02100_amd.profile_summary RESULTS_DB [--top N] [--grids G]
 
 Prints, per kernel name, the number of dispatches, total and average
 duration, and the same split by launch grid (which separates the levels of
@@ -13,7 +13,7 @@ import sqlite3
 from collections import defaultdict
 
 
-def summarise(db_path: str, top: int = 12) -> str:
+def summarise(db_path: str, top: int = 12, grids_per_kernel: int = 6) -> str:
     db = sqlite3.connect(db_path)
     rows = db.execute("select name, duration, grid_x, grid_y, grid_z, workgroup_x from kernels").fetchall()
     by_name = defaultdict(list)
@@ -33,7 +33,7 @@ def summarise(db_path: str, top: int = 12) -> str:
     lines.append("# split by launch grid (grid_x, grid_y, grid_z in work-items; workgroup size)")
     for n in names[:4]:
         grids = sorted((k for k in by_grid if k[0] == n), key=lambda k: -(k[1] * k[2] * k[3]))
-        for k in grids[:6]:
+        for k in grids[:grids_per_kernel]:
             d = by_grid[k]
             lines.append(f"{n[:60]:<60} grid=({k[1]},{k[2]},{k[3]}) wg={k[4]} calls={len(d)} "
                          f"avg_us={sum(d) / len(d) / 1e3:.2f}")
@@ -44,5 +44,6 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("db")
     ap.add_argument("--top", type=int, default=12)
+    ap.add_argument("--grids", type=int, default=6, help="launch grids listed per kernel (largest first)")
     a = ap.parse_args()
-    print(summarise(a.db, a.top))
+    print(summarise(a.db, a.top, a.grids))

@@ -84,17 +84,19 @@ def test_batched_solve_odd_layers(vps):
 
 
 def test_batched_even_layers_full_size(vps):
-    """3D Q4 on 128^3 cells, FP32, slabs of 16 vertex layers: the same bits as whole colors."""
+    """3D Q4 on 128^3 cells, FP32, slabs of 16 vertex layers and of the benchmark's slab size: the same bits
+    as whole colors."""
     import torch
     k, N = 4, 128
     say("batched full size")
     b = vi.seeded_vector(3, k, N, 5)
     u0 = vi.seeded_vector(3, k, N, 105)
     out = []
-    for bl in (0, 16):
+    for bl in (0, 16, vi.WORKLOADS["poisson3d_q4_n128"]["batch_layers"]):
         with vps.Context(3, k, N, 1, vcycle_dtype="f32", batch_layers=bl) as ctx:
             u = dev(u0, torch.float32)
             ctx.smooth(0, u, dev(b, torch.float32), sweeps=1)
             out.append(host(u))
             del u
     assert np.array_equal(out[0], out[1])
+    assert np.array_equal(out[0], out[2])

@@ -123,12 +123,14 @@ def test_residual_vanishes_on_color_interiors_full_size(vps):
 
 
 def test_solve_full_size_host_recheck(vps):
-    """3D Q4, 128^3 cells, 6 levels, V(2,2), FP32 V-cycle in FP64 flexible CG: true residual on the host."""
+    """3D Q4, 128^3 cells, 6 levels, V(2,2), FP32 V-cycle in FP64 flexible CG, the slabs the benchmark
+    sweeps: true residual on the host."""
     import torch
     w = vi.WORKLOADS["poisson3d_q4_n128"]
     say("full-size solve")
     b = vi.seeded_vector(3, w["degree"], w["n_cells"], w["rhs_seed"])
-    with vps.Context(3, w["degree"], w["n_cells"], w["levels"], w["pre"], w["post"], vcycle_dtype=w["vcycle"]) as ctx:
+    with vps.Context(3, w["degree"], w["n_cells"], w["levels"], w["pre"], w["post"], vcycle_dtype=w["vcycle"],
+                     batch_layers=w["batch_layers"]) as ctx:
         x = torch.empty(b.size, dtype=torch.float64, device="cuda")
         info = ctx.solve(dev(b), x, rtol=1e-10, maxit=50)
         xs = host(x)

@@ -109,12 +109,12 @@ WORKLOADS = {
                              vcycle="f64", coef="learned", rhs_seed=4, u0_seed=104,
                              rho_seed=4, train_seed_base=1000, train_patches=200_000),
     # batched color sweeps: each workgroup a batch of same-color patches (a row of 7 x-adjacent
-    # patches on the large levels), and on the finest level all colors of a slab of 32 vertex layers
-    # in turn (Algorithm 5, the same iterate); whole colors are timed beside it.  The FP64 reference
-    # sweeps whole colors (measured faster there)
+    # patches on the large levels), and on the finest level all colors of a slab of 44 vertex layers
+    # in turn (Algorithm 5, the same iterate; 3 slabs); whole colors are timed beside it.  The FP64
+    # reference sweeps whole colors (measured faster there)
     "poisson3d_q4_n128": dict(dim=3, degree=4, n_cells=128, levels=6, pre=2, post=2,
                               vcycle="f32", coef="const", rhs_seed=5, u0_seed=105,
-                              batch_layers=32, batch_layers_f64=0),
+                              batch_layers=44, batch_layers_f64=0),
     # the paper's own shapes (Poisson, a single 2^d-cell patch refined 10 times in 2D and 6 times
     # in 3D; multigrid down to that patch), FP64 as in the paper
     "paper2d_q3_n2048": dict(dim=2, degree=3, n_cells=2048, levels=11, pre=1, post=1,
