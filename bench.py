@@ -120,7 +120,7 @@ def oracle_child(n_cells: int, degree: int, dim: int, budget_s: float):
     sweeps, t = 0, 0.0
     while t < budget_s or sweeps < 1:
         t1 = time.perf_counter()
-        u = smoother.sweep_alg3(A, b, u, P, S)
+        u = smoother.sweep_colorized(A, b, u, P, S)
         t += time.perf_counter() - t1
         sweeps += 1
     n = (degree * n_cells + 1) ** dim

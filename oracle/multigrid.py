@@ -20,7 +20,7 @@ import scipy.linalg as sla
 
 from .assemble import assemble, assemble_kron
 from .mesh import free_mask_flat, coarsen_cells
-from .smoother import Patches, LocalSolvers, sweep_alg3
+from .smoother import Patches, LocalSolvers, sweep_colorized
 from .transfer import prolongation
 
 
@@ -47,7 +47,7 @@ class Level:
 
     def smooth(self, b, u, sweeps, reverse):
         for _ in range(sweeps):
-            u = sweep_alg3(self.A, b, u, self.patches, self.solvers, reverse)
+            u = sweep_colorized(self.A, b, u, self.patches, self.solvers, reverse)
         return u
 
 

@@ -7,14 +7,16 @@ Definitions followed (Sections 2.1 and 3):
 * smoother (eq:s-ell): the product over patches of (I - P_j), applied to the
   error, i.e. u <- u + Pi_j^T B_j Pi_j (b - A u) patch after patch;
 * colored form (eq:colorized): within one color the patches have disjoint
-  interiors and do not read each other's writes, so the color may be done as
-  one global residual followed by all its patch solves (Algorithm 3).
+  interiors and do not read each other's writes, so one factor per color,
+  u <- u + (sum_{j in C_k} Pi_j^T B_j Pi_j)(b - A u), gives the same iterate.
 
-``sweep_alg3`` is the oracle of a sweep; ``sweep_alg1`` (global residual per
-patch, Algorithm 1) and ``sweep_alg2`` (local residual from the patch's own
-element matrices, Algorithm 2) exist for the order-equivalence pins on tiny
-meshes.  Patch order: colors ascending for a forward sweep, descending for a
-reverse sweep; inside a color the order is irrelevant.
+``sweep_colorized`` (eq:colorized, one factor per color) is the oracle of a
+sweep; ``sweep_product`` (eq:s-ell, one factor per patch) and
+``sweep_local_residual`` (eq:s-ell with the residual formed from the patch's
+own cells, Section 3.1) exist for the order-equivalence pins on tiny meshes;
+``sweep_batched`` takes the factors of eq:colorized over the (batch, color)
+sets of Section 4.1.  Patch order: colors ascending for a forward sweep,
+descending for a reverse sweep; inside a color the order is irrelevant.
 """
 from __future__ import annotations
 
@@ -180,21 +182,48 @@ class LocalSolvers:
         return self.S @ (s * (self.S.T @ r))
 
 
-def apply_color(A, b, u, patches: Patches, solvers: LocalSolvers, color: int) -> np.ndarray:
-    """One color of the colored smoother: global residual, then all patch solves."""
-    u = np.array(u, dtype=np.float64, copy=True)
+def group_factor(A, b, u, patches: Patches, solvers: LocalSolvers, group) -> np.ndarray:
+    """One factor of the colorized product (eq:colorized) for the index set ``group``.
+
+    Returns u + (sum_{j in group} Pi_j^T B_j Pi_j)(b - A u): the residual of
+    the current iterate, restricted to each patch interior (Pi_j), mapped by
+    the local solver B_j (eq:main:2, with b - A u in place of A v) and
+    embedded back (Pi_j^T).  For a single patch this is the factor I - P_j of
+    eq:s-ell applied to the error.
+    """
     r = b - A @ u
-    for j in patches.by_color[color]:
+    d = np.zeros_like(r)
+    for j in group:
         I = patches.interior[j]
-        u[I] += solvers.apply(j, r[I])
+        d[I] += solvers.apply(j, r[I])
+    return np.asarray(u, dtype=np.float64) + d
+
+
+def apply_color(A, b, u, patches: Patches, solvers: LocalSolvers, color: int) -> np.ndarray:
+    """The factor of eq:colorized for one color C_k (its patches have disjoint interiors)."""
+    return group_factor(A, b, u, patches, solvers, patches.by_color[color])
+
+
+def patch_sequence(patches: Patches, reverse: bool = False):
+    """Patch order of one sweep: colors ascending (descending if reverse), inside a color by index."""
+    return [j for c in colors_in_order(patches.dim, reverse) for j in patches.by_color[c]]
+
+
+def sweep_product(A, b, u, patches: Patches, solvers: LocalSolvers, reverse: bool = False) -> np.ndarray:
+    """eq:s-ell: one factor (I - P_j) per patch, the residual recomputed before each (Algorithm 1 computes
+    this; tiny meshes only)."""
+    for j in patch_sequence(patches, reverse):
+        u = group_factor(A, b, u, patches, solvers, [j])
     return u
 
 
-def sweep_alg3(A, b, u, patches: Patches, solvers: LocalSolvers, reverse: bool = False) -> np.ndarray:
-    """Separated, colorized smoother (Algorithm 3): one sweep over all colors."""
+def sweep_colorized(A, b, u, patches: Patches, solvers: LocalSolvers, reverse: bool = False) -> np.ndarray:
+    """eq:colorized: one factor per color, colors ascending (descending if reverse).  Equal to eq:s-ell in
+    the same patch order because same-color patches do not read each other's writes (Algorithms 3 and 4
+    compute this)."""
     for c in colors_in_order(patches.dim, reverse):
         u = apply_color(A, b, u, patches, solvers, c)
-    return u
+    return np.array(u, dtype=np.float64, copy=True)
 
 
 def batch_of(patches: Patches, j: int, batch_layers: int) -> int:
@@ -203,14 +232,9 @@ def batch_of(patches: Patches, j: int, batch_layers: int) -> int:
 
 
 def batched_order(patches: Patches, batch_layers: int, reverse: bool = False):
-    """The (batch, color) groups of the batch-processing smoother (Algorithm 5, Section 4.1).
-
-    Patches are in lexicographic order (slowest direction last), grouped by
-    color with that order kept, and each color is cut into batches of whole
-    layers of patches along the slowest direction; the outer loop is over
-    batches, the inner one over colors.  The reverse sweep is the whole
-    sequence backwards.
-    """
+    """Index sets of batch processing (Section 4.1): each color cut into batches of whole patch layers along
+    the slowest direction (lexicographic order kept), the batches outermost, the colors inside.  The
+    reverse sweep takes the sets backwards."""
     nb = (patches.n_cells - 2) // batch_layers + 1
     groups = []
     for bi in range(nb):
@@ -221,55 +245,36 @@ def batched_order(patches: Patches, batch_layers: int, reverse: bool = False):
 
 def sweep_batched(A, b, u, patches: Patches, solvers: LocalSolvers, batch_layers: int,
                   reverse: bool = False) -> np.ndarray:
-    """Batch-processing combined colorized smoother (Algorithm 5) in the Algorithm 3 form per group."""
+    """eq:colorized with the (batch, color) index sets of Section 4.1 as the factors (Algorithm 5 computes
+    this)."""
     u = np.array(u, dtype=np.float64, copy=True)
     for group in batched_order(patches, batch_layers, reverse):
-        if not group:
-            continue
-        r = b - A @ u
-        for j in group:
-            I = patches.interior[j]
-            u[I] += solvers.apply(j, r[I])
+        if group:
+            u = group_factor(A, b, u, patches, solvers, group)
     return u
 
 
-def sweep_alg1(A, b, u, patches: Patches, solvers: LocalSolvers, reverse: bool = False) -> np.ndarray:
-    """Algorithm 1: the global residual recomputed before every patch (tiny meshes)."""
-    u = np.array(u, dtype=np.float64, copy=True)
-    for c in colors_in_order(patches.dim, reverse):
-        for j in patches.by_color[c]:
-            r = b - A @ u
-            I = patches.interior[j]
-            u[I] += solvers.apply(j, r[I])
-    return u
-
-
-def sweep_alg2(b, u, patches: Patches, rho=None, reverse: bool = False) -> np.ndarray:
-    """Algorithm 2: gather, local residual from the patch's cells, exact local solve, scatter.
-
-    Uses only the patch's element matrices (no global matrix): the local
-    residual is b_j - (Abar_j ubar_j) restricted to the interior rows
-    (eq:main:4), the solve uses the interior block of the same local operator.
-    """
+def sweep_local_residual(b, u, patches: Patches, rho=None, reverse: bool = False) -> np.ndarray:
+    """eq:s-ell with the residual of each patch formed locally (Section 3.1): gather the closure (eq:gather),
+    r_j = b_j - Abar_j ubar_j from the patch's own cells restricted to the interior rows (eq:main:4),
+    d_j = A_j^{-1} r_j with A_j the interior block of the same local operator, scatter (eq:scatter).
+    No global matrix is used (Algorithm 2 computes this)."""
     dim, k, n = patches.dim, patches.k, patches.n_cells
     h = 1.0 / n
     u = np.array(u, dtype=np.float64, copy=True)
     inner = closure_interior_positions(dim, k)
     rho_flat = None if rho is None else np.asarray(rho, dtype=np.float64).reshape(-1)
     const_op = None
-    for c in colors_in_order(dim, reverse):
-        for j in patches.by_color[c]:
-            v = patches.verts[j]
-            if rho_flat is None:
-                if const_op is None:
-                    const_op = patch_closure_operator(dim, k, h)
-                Abar = const_op
-            else:
-                Abar = patch_closure_operator(dim, k, h, rho_flat[patches.cells(j)])
-            clo = patch_closure(dim, k, n, v)
-            I = patch_interior(dim, k, n, v)
-            ubar = u[clo]
-            r = b[I] - Abar[inner] @ ubar
-            d = np.linalg.solve(Abar[np.ix_(inner, inner)], r)
-            u[I] += d
+    for j in patch_sequence(patches, reverse):
+        v = patches.verts[j]
+        if rho_flat is None:
+            if const_op is None:
+                const_op = patch_closure_operator(dim, k, h)
+            Abar = const_op
+        else:
+            Abar = patch_closure_operator(dim, k, h, rho_flat[patches.cells(j)])
+        clo = patch_closure(dim, k, n, v)
+        I = patch_interior(dim, k, n, v)
+        r = b[I] - Abar[inner] @ u[clo]
+        u[I] += np.linalg.solve(Abar[np.ix_(inner, inner)], r)
     return u

@@ -205,6 +205,7 @@ def save_params(path: str, params) -> None:
     np.save(path, params.detach().cpu().numpy() if hasattr(params, "detach") else np.asarray(params))
 
 
-def load_params(path: str):
+def load_params(path: str, device: str = "cuda"):
+    """Parameters written by save_params (a plain .npy array; nothing in the file is executed)."""
     import torch
-    return torch.from_numpy(np.load(path, allow_pickle=False).astype(np.float32)).to("cuda")
+    return torch.from_numpy(np.load(path, allow_pickle=False).astype(np.float32)).to(device)

@@ -27,7 +27,7 @@ def test_batched_sweep_odd_layers(vps, dim, k, N, B, reverse):
     b = vi.seeded_vector(dim, k, N, 91)
     u0 = vi.seeded_vector(dim, k, N, 92)
     want = smoother.sweep_batched(A, b, u0, P, S, B, reverse)
-    assert rel(want, smoother.sweep_alg3(A, b, u0, P, S, reverse)) > 1e-8  # a different iterate
+    assert rel(want, smoother.sweep_colorized(A, b, u0, P, S, reverse)) > 1e-8  # a different iterate
     with vps.Context(dim, k, N, 1, batch_layers=B) as ctx:
         u = dev(u0)
         ctx.smooth(0, u, dev(b), sweeps=1, reverse=reverse)
@@ -66,7 +66,7 @@ def test_batched_small_level_sweeps_whole_colors(vps):
     with vps.Context(3, k, N, 1, batch_layers=B) as ctx:
         u = dev(u0)
         ctx.smooth(0, u, dev(b), sweeps=1)
-        assert rel(host(u), smoother.sweep_alg3(A, b, u0, P, S)) <= 1e-12
+        assert rel(host(u), smoother.sweep_colorized(A, b, u0, P, S)) <= 1e-12
 
 
 def test_batched_solve_odd_layers(vps):

@@ -57,7 +57,7 @@ def test_learned_scaling_smooth(vps, dim, k, N):
         ctx.set_patch_scaling(0, dev(scal, torch.float32))
         u = dev(u0)
         ctx.smooth(0, u, dev(b), sweeps=1)
-        want = smoother.sweep_alg3(A, b, u0, P, S)
+        want = smoother.sweep_colorized(A, b, u0, P, S)
         assert rel(host(u), want) <= 1e-12
 
 
@@ -146,7 +146,7 @@ def test_infer_patches_and_fallback(vps):
         assert fb == 0
         u = dev(u0)
         ctx.smooth(0, u, dev(b), sweeps=1)
-        assert rel(host(u), smoother.sweep_alg3(A, b, u0, P, S)) <= 1e-5
+        assert rel(host(u), smoother.sweep_colorized(A, b, u0, P, S)) <= 1e-5
         bad = p.copy()
         bad[:] = np.nan
         fb = ctx.mlp_infer_patches(0, dev(bad, torch.float32))
@@ -155,7 +155,7 @@ def test_infer_patches_and_fallback(vps):
         S2 = smoother.LocalSolvers(A, P, "mean", rho=rho)
         u = dev(u0)
         ctx.smooth(0, u, dev(b), sweeps=1)
-        assert rel(host(u), smoother.sweep_alg3(A, b, u0, P, S2)) <= 1e-12
+        assert rel(host(u), smoother.sweep_colorized(A, b, u0, P, S2)) <= 1e-12
 
 
 def test_learned_scaling_gain_on_held_out_rough_field(vps):

@@ -53,7 +53,7 @@ def test_pair_sweep_fp32(vps, k, N, reverse):
     S = smoother.LocalSolvers(A, P, "shared")
     b = vi.seeded_vector(3, k, N, 73).astype(np.float32).astype(np.float64)
     u0 = vi.seeded_vector(3, k, N, 74).astype(np.float32).astype(np.float64)
-    want = smoother.sweep_alg3(A, b, u0, P, S, reverse=reverse)
+    want = smoother.sweep_colorized(A, b, u0, P, S, reverse=reverse)
     out = {}
     for ppw in (1, 2):
         with vps.Context(3, k, N, 1, vcycle_dtype="f32", patches_per_wave=ppw) as ctx:
@@ -103,7 +103,7 @@ def test_pair_batched_fp64_matches_whole_colors(vps):
     A = assemble.assemble_kron(3, k, N)
     P = smoother.Patches(3, k, N)
     S = smoother.LocalSolvers(A, P, "shared")
-    want = smoother.sweep_alg3(A, b, u0, P, S)
+    want = smoother.sweep_colorized(A, b, u0, P, S)
     assert rel(out[0], want) <= 1e-12
     assert rel(out[2], want) <= 1e-12
 
@@ -139,7 +139,7 @@ def test_single_patch_domain_fp64(vps, k, form):
     S = smoother.LocalSolvers(A, P, "shared")
     b = vi.seeded_vector(3, k, N, 81)
     u0 = vi.seeded_vector(3, k, N, 82)
-    want = smoother.sweep_alg3(A, b, u0, P, S)
+    want = smoother.sweep_colorized(A, b, u0, P, S)
     kw = dict(wave=dict(patches_per_wave=1), pair=dict(patches_per_wave=2), separated=dict(algorithm="separated"))[form]
     with vps.Context(3, k, N, 1, **kw) as ctx:
         u = dev(u0)

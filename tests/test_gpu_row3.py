@@ -54,7 +54,7 @@ def test_row3_sweep_fp32(vps, k, N, reverse):
     S = smoother.LocalSolvers(A, P, "shared")
     b = vi.seeded_vector(3, k, N, 173).astype(np.float32).astype(np.float64)
     u0 = vi.seeded_vector(3, k, N, 174).astype(np.float32).astype(np.float64)
-    want = smoother.sweep_alg3(A, b, u0, P, S, reverse=reverse)
+    want = smoother.sweep_colorized(A, b, u0, P, S, reverse=reverse)
     out = {}
     for ppw in (1, 3):
         with vps.Context(3, k, N, 1, vcycle_dtype="f32", patches_per_wave=ppw) as ctx:
@@ -81,6 +81,6 @@ def test_row3_batched_fp32_matches_whole_colors(vps):
     A = assemble.assemble_kron(3, k, N)
     P = smoother.Patches(3, k, N)
     S = smoother.LocalSolvers(A, P, "shared")
-    want = smoother.sweep_alg3(A, b, u0, P, S)
+    want = smoother.sweep_colorized(A, b, u0, P, S)
     assert rel(out[0], want) <= 2e-5
     assert rel(out[2], want) <= 2e-5

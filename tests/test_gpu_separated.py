@@ -28,7 +28,7 @@ def test_separated_sweep_fp64(vps, k, N, smin, reverse):
     S = smoother.LocalSolvers(A, P, "shared")
     b = vi.seeded_vector(3, k, N, 51)
     u0 = vi.seeded_vector(3, k, N, 52)
-    want = smoother.sweep_alg3(A, b, u0, P, S, reverse=reverse)
+    want = smoother.sweep_colorized(A, b, u0, P, S, reverse=reverse)
     with vps.Context(3, k, N, 1, algorithm="separated", stream_min_cells=smin) as ctx:
         u = dev(u0)
         ctx.smooth(0, u, dev(b), sweeps=1, reverse=reverse)

@@ -48,8 +48,8 @@ def test_sweep_fp64(vps, dim, k, N, reverse):
     A, P, S = _oracle(dim, k, N)
     b = vi.seeded_vector(dim, k, N, 3)
     u0 = vi.seeded_vector(dim, k, N, 4)
-    want = smoother.sweep_alg3(A, b, u0, P, S, reverse)
-    want = smoother.sweep_alg3(A, b, want, P, S, reverse)
+    want = smoother.sweep_colorized(A, b, u0, P, S, reverse)
+    want = smoother.sweep_colorized(A, b, want, P, S, reverse)
     with vps.Context(dim, k, N, 1) as ctx:
         u = dev(u0)
         ctx.smooth(0, u, dev(b), sweeps=2, reverse=reverse)
@@ -85,7 +85,7 @@ def test_fp32_sweep_close_to_fp64(vps):
     A, P, S = _oracle(dim, k, N)
     b = vi.seeded_vector(dim, k, N, 7)
     u0 = vi.seeded_vector(dim, k, N, 8)
-    want = smoother.sweep_alg3(A, b, u0, P, S)
+    want = smoother.sweep_colorized(A, b, u0, P, S)
     import torch
     with vps.Context(dim, k, N, 1, vcycle_dtype="f32") as ctx:
         u = dev(u0, torch.float32)

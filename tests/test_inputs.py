@@ -34,3 +34,17 @@ def test_workloads_are_consistent():
         assert w["n_cells"] % 2 ** (w["levels"] - 1) == 0
         # coarsest mesh: 4 cells per direction; the paper's shapes go down to their single patch
         assert w["n_cells"] // 2 ** (w["levels"] - 1) == (2 if name.startswith("paper") else 4)
+
+
+def test_learned_params_save_load_round_trip(tmp_path):
+    """Checkpoint of the MLP parameters: save_params / load_params give back the same FP32 values."""
+    import torch
+    from paper_2407_02100_amd import learned
+    p = learned.init_params(3)
+    assert p.dtype == np.float32 and p.size == 6491
+    path = str(tmp_path / "mlp.npy")
+    learned.save_params(path, torch.from_numpy(p))
+    back = learned.load_params(path, device="cpu")
+    assert back.dtype == torch.float32 and np.array_equal(back.numpy(), p)
+    learned.save_params(path, p)  # plain arrays too
+    assert np.array_equal(learned.load_params(path, device="cpu").numpy(), p)

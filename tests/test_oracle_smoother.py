@@ -46,7 +46,7 @@ def test_single_patch_sweep_is_exact_solve(dim, k):
     assert len(P) == 1
     b = vi.seeded_vector(dim, k, 2, 1)
     u0 = vi.seeded_vector(dim, k, 2, 2)
-    u = smoother.sweep_alg3(A, b, u0, P, S)
+    u = smoother.sweep_colorized(A, b, u0, P, S)
     free = mesh.free_mask_flat(dim, k, 2)
     x = np.zeros_like(b)
     x[free] = np.linalg.solve(A.toarray()[np.ix_(free, free)], b[free])
@@ -59,7 +59,7 @@ def test_k1_is_multicolor_gauss_seidel(dim, N):
     A, P, S = _setup(dim, 1, N)
     b = vi.seeded_vector(dim, 1, N, 3)
     u0 = vi.seeded_vector(dim, 1, N, 4)
-    u = smoother.sweep_alg3(A, b, u0, P, S)
+    u = smoother.sweep_colorized(A, b, u0, P, S)
     order = np.concatenate([np.concatenate([P.interior[j] for j in P.by_color[c]]) for c in range(2 ** dim)])
     Ap = A[order][:, order].tocsr()
     L = sp.tril(Ap, format="csr")
@@ -76,9 +76,9 @@ def test_alg1_alg2_alg3_agree(dim, k, N, reverse):
     A, P, S = _setup(dim, k, N)
     b = vi.seeded_vector(dim, k, N, 5)
     u0 = vi.seeded_vector(dim, k, N, 6)
-    u1 = smoother.sweep_alg1(A, b, u0, P, S, reverse)
-    u2 = smoother.sweep_alg2(b, u0, P, reverse=reverse)
-    u3 = smoother.sweep_alg3(A, b, u0, P, S, reverse)
+    u1 = smoother.sweep_product(A, b, u0, P, S, reverse)
+    u2 = smoother.sweep_local_residual(b, u0, P, reverse=reverse)
+    u3 = smoother.sweep_colorized(A, b, u0, P, S, reverse)
     sc = np.abs(u3).max()
     assert np.abs(u1 - u3).max() <= 1e-13 * sc
     assert np.abs(u2 - u3).max() <= 1e-13 * sc
@@ -90,8 +90,8 @@ def test_alg2_variable_coefficient_matches_alg3():
     A, P, S = _setup(dim, k, N, rho=rho)
     b = vi.seeded_vector(dim, k, N, 5)
     u0 = vi.seeded_vector(dim, k, N, 6)
-    u2 = smoother.sweep_alg2(b, u0, P, rho=rho)
-    u3 = smoother.sweep_alg3(A, b, u0, P, S)
+    u2 = smoother.sweep_local_residual(b, u0, P, rho=rho)
+    u3 = smoother.sweep_colorized(A, b, u0, P, S)
     assert np.abs(u2 - u3).max() <= 1e-13 * np.abs(u3).max()
 
 
@@ -190,7 +190,7 @@ def test_batched_sweep_one_batch_is_colorized(dim, k, N):
     b = vi.seeded_vector(dim, k, N, 83)
     u0 = vi.seeded_vector(dim, k, N, 84)
     for rev in (False, True):
-        assert np.allclose(smoother.sweep_batched(A, b, u0, P, S, N, rev), smoother.sweep_alg3(A, b, u0, P, S, rev),
+        assert np.allclose(smoother.sweep_batched(A, b, u0, P, S, N, rev), smoother.sweep_colorized(A, b, u0, P, S, rev),
                            rtol=0, atol=1e-13)
 
 
@@ -212,7 +212,7 @@ def test_batched_sweep_even_layers_keep_the_colorized_iterate(B, same):
     us[free] = spla.spsolve(A[free][:, free].tocsc(), b[free])
     energy = lambda v: float((us - v) @ (A @ (us - v)))
     ub = smoother.sweep_batched(A, b, u0, P, S, B)
-    uc = smoother.sweep_alg3(A, b, u0, P, S)
+    uc = smoother.sweep_colorized(A, b, u0, P, S)
     if same:
         assert np.array_equal(ub, uc)
     else:
