@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "patch_sweep_traffic.json")
+TRAFFIC_FILE_F64 = os.path.join(ROOT, "profiles", "patch_sweep_traffic_f64.json")
 
 from paper_2407_02100_amd.traffic_probe import kernel_source_hash  # noqa: E402  (hash of the smoother sources)
 
@@ -75,6 +76,18 @@ def sweep_bytes(dim: int, k: int, n: int, word: int, batch_layers: int = 0) -> i
                for clo, inner in color_counts(dim, k, n, lo, hi))
 
 
+def traffic_per_launch(path: str, workload: str, batch_layers: int, dtype: str):
+    """Measured HBM bytes per launch of the smoother from a committed rocprofv3 summary, or None when the
+    summary is missing or was taken with other sources, another workload, batch size or precision."""
+    if not os.path.exists(path):
+        return None
+    tr = json.load(open(path))
+    if (tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("workload") == workload
+            and tr.get("batch_layers", 0) == batch_layers and tr.get("dtype", "f32") == dtype):
+        return tr.get("bytes_per_launch")
+    return None
+
+
 def finest_smoother_kernel(dim: int, k: int, n_cells: int, vcycle: str, coef: str) -> str:
     """The smoother kernel the library's automatic choice (vps_config.patches_per_wave = 0) runs on a level."""
     if coef != "const":
@@ -104,11 +117,26 @@ def sweep_bytes_separated(dim: int, k: int, n: int, word: int) -> int:
 
 
 # ---------------------------------------------------------------------------
-# CPU baseline: the oracle (FP64 NumPy/SciPy, Algorithm 3 with dense patch
-# solves) timed on a bounded sample of the same problem family.
+# CPU baseline: the oracle (FP64 NumPy/SciPy: assembled CSR operator, dense
+# Cholesky patch solves, eq:colorized one factor per color) timed on the host
+# cores, in a child process that touches no GPU.  The headline value is its
+# sweep rate on a bounded sample of the 3D Q4 family; beside it, the sweep
+# and the multigrid-preconditioned CG solve of the 2D Q2 32^2 workload (whole)
+# and of 16^3 samples of the 3D Q4 32^3 and variable-coefficient Q2 64^3
+# workloads (their full sizes need tens of GB of CSR matrix and minutes).
+
+def _median3(fn, reps=3):
+    ts = []
+    out = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[1], out
+
 
 def oracle_child(n_cells: int, degree: int, dim: int, budget_s: float):
-    from oracle import assemble, smoother
+    from oracle import assemble, multigrid, smoother
     import vps_inputs as vi
     t0 = time.perf_counter()
     A = assemble.assemble_kron(dim, degree, n_cells)
@@ -124,7 +152,26 @@ def oracle_child(n_cells: int, degree: int, dim: int, budget_s: float):
         t += time.perf_counter() - t1
         sweeps += 1
     n = (degree * n_cells + 1) ** dim
-    print(json.dumps({"dofs": n, "sweeps": sweeps, "seconds": t, "setup_s": setup}))
+    out = {"dofs": n, "sweeps": sweeps, "seconds": t, "setup_s": setup, "protocol": {}}
+    # sweep and solve per workload (median of 3 each; setup of the hierarchy not timed)
+    cases = [("poisson2d_q2_n32", "poisson2d_q2_n32", 2, 2, 32, 4, None),
+             ("poisson3d_q4_n32", "sample 3D Q4 16^3, 3 levels", 3, 4, 16, 3, None),
+             ("varcoef3d_q2_n64", "sample 3D Q2 16^3, 3 levels, rho = exp(GRF), corr. length 1/8, seed 4", 3, 2, 16, 3,
+              4)]
+    for name, label, d, k, N, L, rho_seed in cases:
+        rho = None if rho_seed is None else vi.rho_cells(N, rho_seed)
+        H = multigrid.Hierarchy(d, k, N, L, rho=rho, use_kron=rho is None)
+        bb = vi.seeded_vector(d, k, N, 1)
+        lev = H.levels[-1]
+        lev.solvers  # factor the local solvers outside the timing
+        uu = vi.seeded_vector(d, k, N, 2)
+        reps = 3 if name == "poisson2d_q2_n32" else 1
+        t_sw, _ = _median3(lambda: lev.smooth(bb, uu, 1, reverse=False))
+        t_so, (x, it, res) = _median3(lambda: multigrid.pcg(H, bb, 1e-10), reps)
+        out["protocol"][name] = {"case": label, "nodes": (k * N + 1) ** d, "sweep_s": t_sw, "solve_s": t_so,
+                                 "iterations": it, "rel_residual_true": res,
+                                 "timing": "median of 3" if reps == 3 else "sweep median of 3, solve once"}
+    print(json.dumps(out))
 
 
 def cpu_baseline(dim: int, degree: int):
@@ -145,10 +192,12 @@ def cpu_baseline(dim: int, degree: int):
     except OSError:
         pass
     return {"value": rate, "unit": "DoF/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle smoother sweeps (Algorithm 3, assembled CSR + dense Cholesky patch solves, FP64, "
-                       f"single thread) on {dim}D Q{degree} with {n_cells}^{dim} cells "
-                       f"({d['dofs']} nodes), {d['sweeps']} sweeps in {d['seconds']:.1f} s; CPU: {cpu}; "
-                       f"host threads available: {len(os.sched_getaffinity(0))}")}
+            "sample": (f"oracle smoother sweeps (eq:colorized, one factor per color: assembled CSR residual + "
+                       f"dense Cholesky patch solves, FP64) on {dim}D Q{degree} with {n_cells}^{dim} cells "
+                       f"({d['dofs']} nodes), {d['sweeps']} sweeps in {d['seconds']:.1f} s; one thread "
+                       f"(OMP/OpenBLAS/MKL threads = 1; SciPy's CSR product is single-threaded anyway); "
+                       f"CPU: {cpu}; host threads available: {len(os.sched_getaffinity(0))}"),
+            "protocol": d["protocol"]}
 
 
 # ---------------------------------------------------------------------------
@@ -326,7 +375,7 @@ def main():
 
     if args.oracle_child:
         n, k, d = args.oracle_child
-        oracle_child(n, k, d, budget_s=12.0)
+        oracle_child(n, k, d, budget_s=8.0)
         return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -402,12 +451,7 @@ def main():
     per_launch_s = t_sm / launches
     achieved = bytes_sweep / lps / per_launch_s / 1e9
 
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        if (tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("workload") == args.workload
-                and tr.get("batch_layers", 0) == bl):
-            traffic = tr.get("bytes_per_launch")
+    traffic = traffic_per_launch(TRAFFIC_FILE, args.workload, bl, w["vcycle"])
 
     f64 = None
     if not args.no_f64_reference and w["vcycle"] == "f32":
@@ -419,11 +463,22 @@ def main():
         i64 = ctx64.solve(b, x, rtol=1e-10, maxit=100)
         t64 = ctx64.timing_get()
         ctx64.close()
+        lps64 = launches_per_sweep(dim, N, bl64)
+        bytes64 = sweep_bytes(dim, k, N, 8, bl64)
+        per64 = t64["smooth_s"][L] / (t64["smooth_sweeps"][L] * lps64)
+        ach64 = bytes64 / lps64 / per64 / 1e9
         f64 = {"solve_s": i64["seconds"], "iterations": i64["iterations"],
                "rel_residual_true": i64["rel_residual_true"],
                "smoother_dof_per_s": n * t64["smooth_sweeps"][L] / t64["smooth_s"][L],
-               "smoother_gbs": sweep_bytes(dim, k, N, 8, bl64) * t64["smooth_sweeps"][L] / t64["smooth_s"][L] / 1e9,
-               "batch_layers": bl64}
+               "smoother_gbs": bytes64 * t64["smooth_sweeps"][L] / t64["smooth_s"][L] / 1e9,
+               "batch_layers": bl64,
+               "roofline": {"bound": "hbm", "achieved": ach64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": ach64 / HBM_PEAK_GBS,
+                            "traffic": traffic_per_launch(TRAFFIC_FILE_F64, args.workload, bl64, "f64"),
+                            "kernel": f"{finest_smoother_kernel(dim, k, N, 'f64', w.get('coef', 'const'))} "
+                                      "(one color launch of the FP64 smoother, finest level)",
+                            "avg_launch_us": per64 * 1e6, "bytes_per_launch": bytes64 / lps64,
+                            "launches_per_sweep": lps64}}
 
     extras = {} if args.no_extras else run_extras(torch, vps, vi)
 

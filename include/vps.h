@@ -192,25 +192,37 @@ vps_status vps_set_patch_scaling(vps_context* ctx, int level, const float* c_dev
 
 /* ---- level operators ---- */
 
-/* Au = A_l u, matrix-free (sum factorisation over cell tiles). */
+/* Au = A_l u (Section 2, eq:matrix: A_l is the bilinear form applied to the
+ * basis functions of V_l), matrix-free: the cell operator of Appendix A.1 as
+ * the Kronecker sum of 1D mass and stiffness matrices, by sum factorisation.
+ * u, Au: level vectors of dtype t (distinct buffers); Dirichlet rows of Au are 0. */
 vps_status vps_apply(vps_context* ctx, int level, const void* u, void* Au, vps_dtype t);
 
-/* r = b - A_l u. */
+/* r = b - A_l u: the residual that the local solvers act on (Section 2.1, the
+ * remark after eq:main:2 that A v amounts to b - A u).  b, u, r: level vectors
+ * of dtype t; r may not alias u. */
 vps_status vps_residual(vps_context* ctx, int level, const void* b, const void* u, void* r,
                         vps_dtype t);
 
-/* Restriction (the transpose of the prolongation, Section 2):
- * r_coarse = P^T r_fine from level fine_level to fine_level-1. */
+/* Restriction (Section 2: the adjoint of the embedding with respect to the
+ * Euclidean products, i.e. the transpose of the prolongation matrix):
+ * r_coarse = P^T r_fine from level fine_level (>= 1) to fine_level-1.
+ * Vectors of dtype t on their levels; r_coarse is overwritten. */
 vps_status vps_restrict(vps_context* ctx, int fine_level, const void* r_fine, void* r_coarse,
                         vps_dtype t);
 
-/* Prolongation (embedding of the coarse FE space, Section 2):
- * u_fine += P e_coarse from level fine_level-1 to fine_level. */
+/* Prolongation (Section 2: the embedding V_{l-1} -> V_l of the nested spaces;
+ * P[f][c] is the coarse basis function c at fine node f):
+ * u_fine += P e_coarse from level fine_level-1 to fine_level (fine_level >= 1). */
 vps_status vps_prolongate_add(vps_context* ctx, int fine_level, const void* e_coarse,
                               void* u_fine, vps_dtype t);
 
-/* x = A_0^{-1} b on the coarsest level: fast diagonalization of the whole
- * coarse grid for rho = 1, dense explicit inverse otherwise. */
+/* x = A_0^{-1} b on the coarsest level, the exact coarse solve of the V-cycle
+ * (Section 2; its cost is negligible in the time split of Section 4.1):
+ * fast diagonalization (Appendix A.3 applied to the whole coarse grid) for
+ * rho = 1, a dense explicit inverse (host FP64 Cholesky) otherwise.  b, x:
+ * level-0 vectors of dtype t.  VPS_E_UNSUPPORTED if the coarse grid exceeds
+ * the limits given at vps_create. */
 vps_status vps_coarse_solve(vps_context* ctx, const void* b, void* x, vps_dtype t);
 
 /* ---- the smoother (Algorithm 4, combined and colorized) ---- */
@@ -228,13 +240,19 @@ vps_status vps_smooth(vps_context* ctx, int level, void* u, const void* b, vps_d
 
 /* ---- multigrid and the outer solver ---- */
 
-/* z = V r: one V-cycle on the finest level from a zero initial guess,
- * pre_sweeps forward sweeps, coarse correction, post_sweeps reverse sweeps,
- * computed in cfg->vcycle_dtype (FP64 r and z are converted at the ends). */
+/* z = V r: one V-cycle (Section 2: smoother S_l on every level, restriction,
+ * coarse-level recursion, prolongation) on the finest level from a zero
+ * initial guess: pre_sweeps forward sweeps of eq:colorized, residual,
+ * restriction, recursion, prolongate-add, post_sweeps reverse sweeps (which
+ * makes the V-cycle symmetric), the exact coarse solve on level 0; computed in
+ * cfg->vcycle_dtype (FP64 r and z are converted at the ends).  r, z: finest
+ * FP64 vectors (distinct). */
 vps_status vps_vcycle(vps_context* ctx, const double* r, double* z);
 
-/* Solve A u = b (finest level) from u = 0 by CG preconditioned with the
- * V-cycle (flexible CG when the V-cycle runs in FP32), all Krylov vectors,
+/* Solve eq:matrix, A u = b on the finest level, from u = 0 by CG
+ * preconditioned with the V-cycle (the multigrid solver of Section 4.1's
+ * timings; the paper does not name its Krylov method: flexible CG when the
+ * V-cycle runs in FP32), all Krylov vectors,
  * dot products and updates in FP64, until ||b - A u|| <= rtol ||b|| with the
  * true residual recomputed at the end.  Synchronises.  info may be NULL.
  * Returns VPS_E_NOT_CONVERGED after maxit iterations (u holds the iterate),
@@ -243,23 +261,34 @@ vps_status vps_solve(vps_context* ctx, const double* b, double* u, double rtol, 
                      vps_solve_info* info);
 
 /* Stationary iteration u <- u + V(b - A u), `iters` times, starting from the
- * given u (FP64, device).  res_hist (host, iters+1 doubles, may be NULL)
+ * given u (FP64, device): the multigrid method of Section 2 used as a solver,
+ * whose residual ratio per iteration is the convergence factor that judges a
+ * local solver (not in the paper).  res_hist (host, iters+1 doubles, may be NULL)
  * receives ||b - A u||_2 before the first and after every iteration.
  * Synchronises. */
 vps_status vps_vcycle_iterate(vps_context* ctx, const double* b, double* u, int iters,
                               double* res_hist);
 
-/* ---- learned eigenmode scaling (variable coefficient, d = 3) ---- */
+/* ---- learned eigenmode scaling (variable coefficient, d = 3) ----
+ * Not in the paper.  The paper allows approximate local solvers (the remark
+ * after eq:main:2); these calls build one: the fast-diagonalization inverse
+ * of Appendix A.3 (eq:fdm:inverse) formed for the patch mean of rho, with
+ * every eigenmode scaled by a factor that a small MLP predicts from the
+ * patch's cell coefficients.  Every pointer below is a device pointer owned
+ * by the caller, FP32 unless stated. */
 
-/* Features of every patch of a level: x[j][c] = log(rho_c / rhobar_j) over the
- * patch's 2^d cells (lexicographic, x fastest), FP32, n_patches x 2^d. */
+/* Features of every patch of a level (MLP input; not in the paper):
+ * x[j][c] = log(rho_c / rhobar_j) over the patch's 2^d cells (lexicographic,
+ * x fastest), rhobar_j their arithmetic mean, FP32, n_patches x 2^d. */
 vps_status vps_patch_features(vps_context* ctx, int level, float* x_dev);
 
-/* Cell coefficients of every patch of a level: rho8[j][c] for the patch's
- * 2^d cells (lexicographic, x fastest), FP64, n_patches x 2^d (device). */
+/* Cell coefficients of every patch of a level (the cells of the vertex patch
+ * Omega_j, Section 2.1 item 1): rho8[j][c] for the patch's 2^d cells
+ * (lexicographic, x fastest), FP64, n_patches x 2^d (device). */
 vps_status vps_patch_rho8(vps_context* ctx, int level, double* rho8_dev);
 
-/* Features of n arbitrary patches from their cell coefficients:
+/* Features of n arbitrary patches from their cell coefficients (not in the
+ * paper):
  * x[j][c] = log(rho8[j][c] / mean_c rho8[j][c]), FP32, n x 2^d (device). */
 vps_status vps_rho8_features(vps_context* ctx, const double* rho8_dev, long long n, float* x_dev);
 
@@ -274,34 +303,44 @@ vps_status vps_rho8_features(vps_context* ctx, const double* rho8_dev, long long
 vps_status vps_patch_targets(vps_context* ctx, const double* rho8_dev, long long n,
                              double* cstar_dev, float* log_target_dev);
 
-/* MLP n_in -> n_h (tanh) -> n_h (tanh) -> n_out with n_in = 2^d, n_h = 64,
+/* Not in the paper.
+ * MLP n_in -> n_h (tanh) -> n_h (tanh) -> n_out with n_in = 2^d, n_h = 64,
  * n_out = q^d, FP32.  params: flat W1 (n_h x n_in, row-major), b1, W2, b2, W3
  * (n_out x n_h), b3.  x: n x n_in.  y: n x n_out.  act_cache (may be NULL):
  * n x 2 n_h, the two hidden activations, needed by vps_mlp_backward. */
 vps_status vps_mlp_forward(vps_context* ctx, const float* params, const float* x, long long n,
                            float* y, float* act_cache);
 
-/* dy = d(loss)/dy for loss = mean over n x n_out of (y - t)^2; loss_out
+/* Not in the paper.
+ * dy = d(loss)/dy for loss = mean over n x n_out of (y - t)^2; loss_out
  * (device, 1 float, may be NULL) receives the loss. */
 vps_status vps_mlp_loss_grad(vps_context* ctx, const float* y, const float* t, long long n,
                              float* dy, float* loss_out);
 
-/* dparams = gradient of sum(dy * y) w.r.t. params (overwritten). */
+/* Not in the paper.
+ * dparams = gradient of sum(dy * y) w.r.t. params (overwritten); x is the
+ * forward input (the first layer's weight gradient needs it), act_cache the
+ * forward's hidden activations, dy n x n_out.  dparams must not alias params. */
 vps_status vps_mlp_backward(vps_context* ctx, const float* params, const float* x,
                             const float* act_cache, const float* dy, long long n,
                             float* dparams);
 
-/* One Adam step (step counts from 1) on params with moments m, v. */
+/* Not in the paper.
+ * One Adam step (step counts from 1) on params with moments m, v, in place;
+ * params, dparams, m, v: mlp parameter count each. */
 vps_status vps_mlp_adam(vps_context* ctx, float* params, const float* dparams, float* m,
                         float* v, int step, float lr, float b1, float b2, float eps);
 
-/* Run the MLP on every patch of a level and store c = clamp(exp(y), 1/4, 4) as
+/* Not in the paper (the approximate local solver of the remark after
+ * eq:main:2, with eq:fdm:inverse's 1/Lambda_m scaled per mode).
+ * Run the MLP on every patch of a level and store c = clamp(exp(y), 1/4, 4) as
  * the level's scaling; patches with non-finite outputs fall back to c = 1.
  * fallback (host, may be NULL) receives their number.  Synchronises. */
 vps_status vps_mlp_infer_patches(vps_context* ctx, int level, const float* params,
                                  long long* fallback);
 
-/* ---- phase timing (the time split of the multigrid solve) ---- */
+/* ---- phase timing (the time split of the multigrid solve, the analogue of
+ * the split Section 4.1 reports for its solver) ---- */
 
 #define VPS_MAX_LEVELS 16
 

@@ -154,12 +154,22 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
           w.np[e] = a.np[e];
         }
         w.ngx = (a.np[0] + R::G - 1) / R::G;
-        const unsigned long long ng = (unsigned long long)w.ngx * (unsigned)a.np[1] * (unsigned)a.np[2];
-        // the group decomposition divides numbers below ngroups by ngx and np[1]
-        if (ng * (unsigned)w.ngx >= (1ull << 32) || ng * (unsigned)a.np[1] >= (1ull << 32)) return hipErrorInvalidValue;
+        const unsigned long long npatch = (unsigned long long)a.np[0] * (unsigned)a.np[1] * (unsigned)a.np[2];
+        // packed groups (every group but the last holds G patches, a group may continue on the
+        // next row of patches) when a row holds at least G patches, row groups otherwise
+        w.packed = a.np[0] >= R::G ? 1 : 0;
+        const unsigned long long ng = w.packed ? (npatch + R::G - 1) / R::G
+                                               : (unsigned long long)w.ngx * (unsigned)a.np[1] * (unsigned)a.np[2];
+        // the group decomposition divides numbers below ngroups by ngx and np[1] (row groups) or
+        // numbers below npatch by np[0] and np[1] (packed)
+        if (ng * (unsigned)w.ngx >= (1ull << 32) || ng * (unsigned)a.np[1] >= (1ull << 32) ||
+            npatch * (unsigned)a.np[0] >= (1ull << 32) || npatch * (unsigned)a.np[1] >= (1ull << 32))
+          return hipErrorInvalidValue;
         w.ngroups = (unsigned)ng;
+        w.npatch = (unsigned)npatch;
         w.vec_bytes = (unsigned)vbytes;
         w.magic_g = magic_of((unsigned)w.ngx);
+        w.magic_x = magic_of((unsigned)a.np[0]);
         w.magic_y = magic_of((unsigned)a.np[1]);
         PatchBand<T, K> band;
         if (!make_band<T, K>(L.M[0], L.Kst[0], &band)) return hipErrorInvalidValue;

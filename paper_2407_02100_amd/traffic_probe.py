@@ -31,9 +31,14 @@ COPY_BYTES = 512 * 1024 * 1024  # bytes read by the calibration copy (and writte
 
 
 def kernel_source_hash() -> str:
+    """Hash of every library source (kernels, launchers, host driver) and the C header: a traffic
+    profile taken with other sources is void, whichever file changed the kernel or its launch."""
     h = hashlib.sha256()
-    for f in ("patch_wave.h", "patch_row3.h"):
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+    csrc = os.path.join(HERE, "csrc")
+    files = sorted(f for f in os.listdir(csrc) if f.endswith((".h", ".hip", ".cpp")))
+    for f in files + [os.path.join("..", "..", "include", "vps.h")]:
+        h.update(f.encode())
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -152,6 +152,42 @@ def _dtype_of(t):
     raise VpsError(VPS_E_ARG, f"unsupported dtype {t.dtype}")
 
 
+def _check_args(what, specs, same_dtype=False):
+    """Host-side checks before any call into the library: dtype, element count, then one CUDA device.
+
+    specs: (name, tensor or None, dtype name 'f64'/'f32'/None, element count or None).  A pointer the
+    library reads or writes covers exactly the elements the C ABI documents, so a wrong dtype or size
+    would make a kernel access memory outside the tensor; these are rejected here with VPS_E_ARG.
+    """
+    import torch
+    want = {"f64": torch.float64, "f32": torch.float32}
+    seen = []
+    for name, t, dt, numel in specs:
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor):
+            raise VpsError(VPS_E_ARG, f"{what}: {name} must be a torch tensor")
+        if dt is not None and t.dtype != want[dt]:
+            raise VpsError(VPS_E_ARG, f"{what}: {name} must be {want[dt]}, got {t.dtype}")
+        if t.dtype not in (torch.float64, torch.float32):
+            raise VpsError(VPS_E_ARG, f"{what}: {name} has unsupported dtype {t.dtype}")
+        if numel is not None and t.numel() != numel:
+            raise VpsError(VPS_E_ARG, f"{what}: {name} must have {numel} elements, got {t.numel()}")
+        seen.append((name, t))
+    if same_dtype and len({t.dtype for _, t in seen}) > 1:
+        raise VpsError(VPS_E_ARG, f"{what}: " + ", ".join(f"{n} {t.dtype}" for n, t in seen)
+                       + " must share one dtype")
+    devs = set()
+    for name, t in seen:
+        if not t.is_cuda:
+            raise VpsError(VPS_E_ARG, f"{what}: {name} must live on the GPU")
+        if not t.is_contiguous():
+            raise VpsError(VPS_E_ARG, f"{what}: {name} must be contiguous")
+        devs.add(t.device)
+    if len(devs) > 1:
+        raise VpsError(VPS_E_ARG, f"{what}: tensors on several devices {sorted(map(str, devs))}")
+
+
 def _current_stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -168,7 +204,7 @@ class Context:
                          patches_per_wave, int(bool(vcycle_graph)),
                          wave_rows_2d)
         self.cfg = cfg
-        self.dim, self.degree, self.n_levels = dim, degree, n_levels
+        self._shape(dim, degree, n_cells, n_levels)
         h = _vp()
         st = lib().vps_create(ctypes.byref(cfg), stream if stream is not None else _current_stream(),
                               ctypes.byref(h))
@@ -177,6 +213,23 @@ class Context:
         self.h = h
 
     # -- helpers --
+    def _shape(self, dim, degree, n_cells, n_levels):
+        """Element counts the C ABI documents per level (host arithmetic on the configuration only)."""
+        self.dim, self.degree, self.n_levels = dim, degree, n_levels
+        self.h = None
+        cells = [max(n_cells >> (n_levels - 1 - l), 0) for l in range(n_levels)]
+        self._cells = cells
+        self._nodes = [(degree * c + 1) ** dim for c in cells]
+        self._patches = [max(c - 1, 0) ** dim for c in cells]
+        self._nin = 2 ** dim
+        self._nout = (2 * degree - 1) ** dim
+        self._nparams = mlp_param_count(self._nin, self._nout)
+
+    def _level(self, what, level, lo=0):
+        if not (lo <= level < self.n_levels):
+            raise VpsError(VPS_E_ARG, f"{what}: level {level} outside [{lo}, {self.n_levels})")
+        return level
+
     def _check(self, st, what):
         if st != VPS_OK:
             msg = lib().vps_last_error(self.h).decode() if self.h else ""
@@ -216,43 +269,66 @@ class Context:
 
     # -- set-up --
     def set_coefficient(self, rho_cells):
+        _check_args("vps_set_coefficient", [("rho_cells", rho_cells, "f64", self._cells[-1] ** self.dim)])
         self._check(lib().vps_set_coefficient(self.h, _ptr(rho_cells)), "vps_set_coefficient")
 
     def set_patch_scaling(self, level, c):
+        self._level("vps_set_patch_scaling", level)
+        _check_args("vps_set_patch_scaling", [("c", c, "f32", self._patches[level] * self._nout)])
         self._check(lib().vps_set_patch_scaling(self.h, level, _ptr(c)), "vps_set_patch_scaling")
 
     # -- level operators --
     def apply(self, level, u, Au):
+        n = self._nodes[self._level("vps_apply", level)]
+        _check_args("vps_apply", [("u", u, None, n), ("Au", Au, None, n)], same_dtype=True)
         self._check(lib().vps_apply(self.h, level, _ptr(u), _ptr(Au), _dtype_of(u)), "vps_apply")
 
     def residual(self, level, b, u, r):
+        n = self._nodes[self._level("vps_residual", level)]
+        _check_args("vps_residual", [("b", b, None, n), ("u", u, None, n), ("r", r, None, n)], same_dtype=True)
         self._check(lib().vps_residual(self.h, level, _ptr(b), _ptr(u), _ptr(r), _dtype_of(u)), "vps_residual")
 
     def restrict(self, fine_level, r_fine, r_coarse):
+        f = self._level("vps_restrict", fine_level, lo=1)
+        _check_args("vps_restrict", [("r_fine", r_fine, None, self._nodes[f]),
+                                     ("r_coarse", r_coarse, None, self._nodes[f - 1])], same_dtype=True)
         self._check(lib().vps_restrict(self.h, fine_level, _ptr(r_fine), _ptr(r_coarse), _dtype_of(r_fine)),
                     "vps_restrict")
 
     def prolongate_add(self, fine_level, e_coarse, u_fine):
+        f = self._level("vps_prolongate_add", fine_level, lo=1)
+        _check_args("vps_prolongate_add", [("e_coarse", e_coarse, None, self._nodes[f - 1]),
+                                           ("u_fine", u_fine, None, self._nodes[f])], same_dtype=True)
         self._check(lib().vps_prolongate_add(self.h, fine_level, _ptr(e_coarse), _ptr(u_fine),
                                              _dtype_of(u_fine)), "vps_prolongate_add")
 
     def coarse_solve(self, b, x):
+        _check_args("vps_coarse_solve", [("b", b, None, self._nodes[0]), ("x", x, None, self._nodes[0])],
+                    same_dtype=True)
         self._check(lib().vps_coarse_solve(self.h, _ptr(b), _ptr(x), _dtype_of(b)), "vps_coarse_solve")
 
     # -- smoother --
     def smooth_color(self, level, u, b, color):
+        n = self._nodes[self._level("vps_smooth_color", level)]
+        _check_args("vps_smooth_color", [("u", u, None, n), ("b", b, None, n)], same_dtype=True)
         self._check(lib().vps_smooth_color(self.h, level, _ptr(u), _ptr(b), _dtype_of(u), color),
                     "vps_smooth_color")
 
     def smooth(self, level, u, b, sweeps=1, reverse=False):
+        n = self._nodes[self._level("vps_smooth", level)]
+        _check_args("vps_smooth", [("u", u, None, n), ("b", b, None, n)], same_dtype=True)
         self._check(lib().vps_smooth(self.h, level, _ptr(u), _ptr(b), _dtype_of(u), sweeps, int(reverse)),
                     "vps_smooth")
 
     # -- multigrid / solver --
     def vcycle(self, r, z):
+        n = self._nodes[-1]
+        _check_args("vps_vcycle", [("r", r, "f64", n), ("z", z, "f64", n)])
         self._check(lib().vps_vcycle(self.h, _ptr(r), _ptr(z)), "vps_vcycle")
 
     def solve(self, b, u, rtol=1e-10, maxit=100, check=True):
+        n = self._nodes[-1]
+        _check_args("vps_solve", [("b", b, "f64", n), ("u", u, "f64", n)])
         info = vps_solve_info()
         st = lib().vps_solve(self.h, _ptr(b), _ptr(u), rtol, maxit, ctypes.byref(info))
         if check:
@@ -261,41 +337,67 @@ class Context:
                 "seconds": info.seconds, "fallback_patches": info.fallback_patches}
 
     def vcycle_iterate(self, b, u, iters):
+        n = self._nodes[-1]
+        _check_args("vps_vcycle_iterate", [("b", b, "f64", n), ("u", u, "f64", n)])
         hist = (ctypes.c_double * (iters + 1))()
         self._check(lib().vps_vcycle_iterate(self.h, _ptr(b), _ptr(u), iters, hist), "vps_vcycle_iterate")
         return list(hist)
 
     # -- learned scaling --
     def patch_features(self, level, x):
+        lv = self._level("vps_patch_features", level)
+        _check_args("vps_patch_features", [("x", x, "f32", self._patches[lv] * self._nin)])
         self._check(lib().vps_patch_features(self.h, level, _ptr(x)), "vps_patch_features")
 
     def patch_rho8(self, level, rho8):
+        lv = self._level("vps_patch_rho8", level)
+        _check_args("vps_patch_rho8", [("rho8", rho8, "f64", self._patches[lv] * self._nin)])
         self._check(lib().vps_patch_rho8(self.h, level, _ptr(rho8)), "vps_patch_rho8")
 
     def rho8_features(self, rho8, x):
+        n = rho8.shape[0]
+        _check_args("vps_rho8_features", [("rho8", rho8, "f64", n * self._nin), ("x", x, "f32", n * self._nin)])
         self._check(lib().vps_rho8_features(self.h, _ptr(rho8), rho8.shape[0], _ptr(x)), "vps_rho8_features")
 
     def patch_targets(self, rho8, cstar, log_target=None):
+        n = rho8.shape[0]
+        _check_args("vps_patch_targets", [("rho8", rho8, "f64", n * self._nin), ("cstar", cstar, "f64", n * self._nout),
+                                          ("log_target", log_target, "f32", n * self._nout)])
         self._check(lib().vps_patch_targets(self.h, _ptr(rho8), rho8.shape[0], _ptr(cstar), _ptr(log_target)),
                     "vps_patch_targets")
 
     def mlp_forward(self, params, x, y, act=None):
+        n = x.shape[0]
+        _check_args("vps_mlp_forward", [("params", params, "f32", self._nparams), ("x", x, "f32", n * self._nin),
+                                        ("y", y, "f32", n * self._nout), ("act", act, "f32", n * 2 * 64)])
         self._check(lib().vps_mlp_forward(self.h, _ptr(params), _ptr(x), x.shape[0], _ptr(y), _ptr(act)),
                     "vps_mlp_forward")
 
     def mlp_loss_grad(self, y, t, dy, loss=None):
+        n = y.shape[0]
+        _check_args("vps_mlp_loss_grad", [("y", y, "f32", n * self._nout), ("t", t, "f32", n * self._nout),
+                                          ("dy", dy, "f32", n * self._nout), ("loss", loss, "f32", 1)])
         self._check(lib().vps_mlp_loss_grad(self.h, _ptr(y), _ptr(t), y.shape[0], _ptr(dy), _ptr(loss)),
                     "vps_mlp_loss_grad")
 
     def mlp_backward(self, params, x, act, dy, dparams):
+        n = x.shape[0]
+        _check_args("vps_mlp_backward", [("params", params, "f32", self._nparams), ("x", x, "f32", n * self._nin),
+                                         ("act", act, "f32", n * 2 * 64), ("dy", dy, "f32", n * self._nout),
+                                         ("dparams", dparams, "f32", self._nparams)])
         self._check(lib().vps_mlp_backward(self.h, _ptr(params), _ptr(x), _ptr(act), _ptr(dy), x.shape[0],
                                            _ptr(dparams)), "vps_mlp_backward")
 
     def mlp_adam(self, params, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        P = self._nparams
+        _check_args("vps_mlp_adam", [("params", params, "f32", P), ("g", g, "f32", P), ("m", m, "f32", P),
+                                     ("v", v, "f32", P)])
         self._check(lib().vps_mlp_adam(self.h, _ptr(params), _ptr(g), _ptr(m), _ptr(v), step, lr, b1, b2, eps),
                     "vps_mlp_adam")
 
     def mlp_infer_patches(self, level, params):
+        self._level("vps_mlp_infer_patches", level)
+        _check_args("vps_mlp_infer_patches", [("params", params, "f32", self._nparams)])
         fb = ctypes.c_longlong(0)
         self._check(lib().vps_mlp_infer_patches(self.h, level, _ptr(params), ctypes.byref(fb)),
                     "vps_mlp_infer_patches")
