@@ -242,8 +242,7 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
       const T s2 = lmy + lmx;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        if constexpr (sizeof(T) == 4) W0[q * Q2 + i] = c[q] * __builtin_amdgcn_rcpf(s2 + FS.lam[q]);
-        else W0[q * Q2 + i] = c[q] / (s2 + FS.lam[q]);
+        W0[q * Q2 + i] = c[q] * inv_eig(s2 + FS.lam[q]);
       }
     }
   }

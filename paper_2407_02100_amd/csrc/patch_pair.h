@@ -236,8 +236,7 @@ __global__ void __launch_bounds__(64) patch_pair3_kernel(const PairArgs<T, K> a)
       const T s2 = lmy + lmx;
 #pragma unroll
       for (int jm = 0; jm < Q; ++jm) {
-        if constexpr (sizeof(T) == 4) W0[jm * Q2 + lane] = c[jm] * __builtin_amdgcn_rcpf(s2 + a.lam[jm]);
-        else W0[jm * Q2 + lane] = c[jm] / (s2 + a.lam[jm]);
+        W0[jm * Q2 + lane] = c[jm] * inv_eig(s2 + a.lam[jm]);
       }
     }
     __syncthreads();

@@ -157,8 +157,7 @@ __global__ void __launch_bounds__(64) patch_row2_kernel(const RowArgs<T, K> a) {
     for (int q = 1; q < Q; ++q) lmx = (mx == q) ? a.lam[q] : lmx;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {  // the lane's own column: [p][my][mx]
-      if constexpr (sizeof(T) == 4) W[(pp * Q + q) * Q + mx] = c[q] * __builtin_amdgcn_rcpf(lmx + a.lam[q]);
-      else W[(pp * Q + q) * Q + mx] = c[q] / (lmx + a.lam[q]);
+      W[(pp * Q + q) * Q + mx] = c[q] * inv_eig(lmx + a.lam[q]);
     }
   }
   __syncthreads();

@@ -404,8 +404,7 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
       const T s2 = lmx + a.lam[mz];
 #pragma unroll
       for (int my = 0; my < Q; ++my) {
-        if constexpr (sizeof(T) == 4) c[my] *= __builtin_amdgcn_rcpf(s2 + a.lam[my]);
-        else c[my] /= (s2 + a.lam[my]);
+        c[my] *= inv_eig(s2 + a.lam[my]);
       }
       fdm_backward<T, K>(a.f, c, e[mz]);  // T along y
     }

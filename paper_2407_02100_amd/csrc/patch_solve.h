@@ -101,8 +101,7 @@ __global__ void __launch_bounds__(64) patch_solve3_kernel(const SolveArgs<T, K> 
     const T s2 = pick_lane<T, Q>(a.lam, ly) + pick_lane<T, Q>(a.lam, lx);
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      if constexpr (sizeof(T) == 4) c[j] *= __builtin_amdgcn_rcpf(s2 + a.lam[j]);
-      else c[j] /= (s2 + a.lam[j]);
+      c[j] *= inv_eig(s2 + a.lam[j]);
     }
     fdm_backward<T, K>(a.f, c, d);
 #pragma unroll
