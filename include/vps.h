@@ -325,6 +325,22 @@ vps_status vps_mlp_backward(vps_context* ctx, const float* params, const float* 
                             const float* act_cache, const float* dy, long long n,
                             float* dparams);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same gradient
+ * as vps_mlp_backward, same kernels and same result, but its work memory (the
+ * per-sample deltas and the partial gradients of up to 64 sample splits) is a
+ * static device array of 4 MiB (1 Mi floats) that the library holds on every
+ * GPU it runs on until the process ends, so the call allocates nothing.
+ * n must not exceed (2^20 - 64 P) / 128 samples, P the MLP parameter count
+ * (4946 for 8 -> 64 -> 64 -> 27); larger n returns VPS_E_ARG before any work.
+ * Every call on one GPU uses that GPU's one array: calls that overlap in time
+ * on one GPU (several streams or threads) race and give wrong results; calls
+ * in order on one stream are safe.  Nothing in the array needs clearing (each
+ * call overwrites what it reads). */
+vps_status vps_mlp_backward_noalloc(vps_context* ctx, const float* params, const float* x,
+                                    const float* act_cache, const float* dy, long long n,
+                                    float* dparams);
+
 /* Not in the paper.
  * One Adam step (step counts from 1) on params with moments m, v, in place;
  * params, dparams, m, v: mlp parameter count each. */

@@ -797,6 +797,11 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.dim == 3 && C.coef == VPS_COEF_CONST && C.degree >= 2 && C.degree <= 4 && vbytes >= 4294967296.0)
     return VPS_E_UNSUPPORTED;
 
+  // the static work memory of vps_mlp_backward_noalloc: its device address, once per GPU
+  if (hipError_t e = vps::mlp_scratch_setup(); e != hipSuccess) {
+    g_create_error = std::string("vps_create: hipGetSymbolAddress of the static work memory: ") + hipGetErrorString(e);
+    return VPS_E_HIP;
+  }
   vps_context* c = new vps_context();
   c->cfg = C;
   c->stream = (hipStream_t)hip_stream;
@@ -1335,6 +1340,20 @@ vps_status vps_mlp_backward(vps_context* c, const float* params, const float* x,
   const int nin = 1 << c->cfg.dim, nout = ipow(2 * c->cfg.degree - 1, c->cfg.dim);
   if (vps::mlp_ensure(&c->mlp) != hipSuccess) return fail(c, VPS_E_NOMEM, "MLP work allocation failed");
   VPS_HIP(c, vps::launch_mlp_backward(params, x, act, dy, n, nin, nout, dparams, &c->mlp, c->stream));
+  return VPS_OK;
+}
+
+vps_status vps_mlp_backward_noalloc(vps_context* c, const float* params, const float* x, const float* act,
+                                    const float* dy, long long n, float* dparams) {
+  if (vps_status s = need_mlp_shape(c)) return s;
+  if (!c || !params || !x || !act || !dy || !dparams) return fail(c, VPS_E_ARG, "null argument");
+  if (n <= 0) return fail(c, VPS_E_ARG, "count must be positive");
+  const int nin = 1 << c->cfg.dim, nout = ipow(2 * c->cfg.degree - 1, c->cfg.dim);
+  const long long nmax = vps::mlp_noalloc_max_samples(nin, nout);
+  if (n > nmax)
+    return fail(c, VPS_E_ARG, "vps_mlp_backward_noalloc: " + std::to_string(n) + " samples exceed the " +
+                                  std::to_string(nmax) + " its 4 MiB static work memory holds");
+  VPS_HIP(c, vps::launch_mlp_backward_noalloc(params, x, act, dy, n, nin, nout, dparams, c->stream));
   return VPS_OK;
 }
 

@@ -2,6 +2,7 @@
 // targets, MLP forward/backward/Adam and per-patch inference (FP32 network,
 // FP64 targets).
 #include <cmath>
+#include <mutex>
 
 #include "kernels.h"
 #include "mlp_launch.h"
@@ -487,23 +488,91 @@ hipError_t launch_mlp_loss_grad(const float* y, const float* t, long long n, int
   return e;
 }
 
+namespace {
+
+// split of the samples for the partial gradients: at most 64 splits of >= 256 samples
+long long backward_splits(long long n) {
+  long long nsplit = (n + 255) / 256;
+  return nsplit > 64 ? 64 : nsplit;
+}
+
+// the three backward kernels on caller-provided work memory: delta (n x 2H floats) and
+// partial (splits x parameter count floats), both fully overwritten before they are read
+hipError_t backward_kernels(const float* params, const float* x, const float* act, const float* dy, long long n,
+                            int nin, int nout, float* dparams, float* delta, float* partial, hipStream_t s) {
+  const int np = mlp_param_count(nin, nout);
+  const long long nsplit = backward_splits(n);
+  const long long chunk = (n + nsplit - 1) / nsplit;
+  backward_delta_kernel<<<blocks_for(n), kBlock, 0, s>>>(params, act, dy, n, nin, nout, delta);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 grid((np + kBlock - 1) / kBlock, (unsigned)nsplit);
+  grad_partial_kernel<<<grid, kBlock, 0, s>>>(x, act, dy, delta, n, nin, nout, chunk, partial);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  grad_final_kernel<<<(np + kBlock - 1) / kBlock, kBlock, 0, s>>>(partial, (int)nsplit, np, dparams);
+  return hipGetLastError();
+}
+
+// Work memory of the allocation-free backward (vps_mlp_backward_noalloc): one
+// copy per GPU for the life of the process, shared by every call on that GPU.
+// Host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device (g_scratch_dev), never through the array's name.
+constexpr size_t kScratchFloats = size_t(1) << 20;  // 4 MiB
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+
+}  // namespace
+
 hipError_t launch_mlp_backward(const float* params, const float* x, const float* act, const float* dy, long long n,
                                int nin, int nout, float* dparams, MlpWork* w, hipStream_t s) {
   if (nin > kMlpMaxIn || nout > kMlpMaxOut) return hipErrorInvalidValue;
   hipError_t e = grow(&w->delta, &w->delta_cap, (size_t)n * 2 * H, s);
   if (e != hipSuccess) return e;
   const int np = mlp_param_count(nin, nout);
-  long long nsplit = (n + 255) / 256;
-  if (nsplit > 64) nsplit = 64;
-  const long long chunk = (n + nsplit - 1) / nsplit;
-  if ((e = grow(&w->partial, &w->partial_cap, (size_t)nsplit * np, s)) != hipSuccess) return e;
-  backward_delta_kernel<<<blocks_for(n), kBlock, 0, s>>>(params, act, dy, n, nin, nout, w->delta);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  dim3 grid((np + kBlock - 1) / kBlock, (unsigned)nsplit);
-  grad_partial_kernel<<<grid, kBlock, 0, s>>>(x, act, dy, w->delta, n, nin, nout, chunk, w->partial);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  grad_final_kernel<<<(np + kBlock - 1) / kBlock, kBlock, 0, s>>>(w->partial, (int)nsplit, np, dparams);
-  return hipGetLastError();
+  if ((e = grow(&w->partial, &w->partial_cap, (size_t)backward_splits(n) * np, s)) != hipSuccess) return e;
+  return backward_kernels(params, x, act, dy, n, nin, nout, dparams, w->delta, w->partial, s);
+}
+
+long long mlp_noalloc_max_samples(int nin, int nout) {
+  const long long np = mlp_param_count(nin, nout);
+  const long long room = (long long)kScratchFloats - 64 * np;  // partials of the largest split count
+  return room > 0 ? room / (2 * H) : 0;
+}
+
+hipError_t mlp_scratch_setup() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_dev[dev] = static_cast<float*>(ptr);
+  return hipSuccess;
+}
+
+hipError_t launch_mlp_backward_noalloc(const float* params, const float* x, const float* act, const float* dy,
+                                       long long n, int nin, int nout, float* dparams, hipStream_t s) {
+  if (nin > kMlpMaxIn || nout > kMlpMaxOut) return hipErrorInvalidValue;
+  if (n <= 0 || n > mlp_noalloc_max_samples(nin, nout)) return hipErrorInvalidValue;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  float* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev >= 0 && dev < kMaxDevices) base = g_scratch_dev[dev];
+  }
+  if (!base) return hipErrorNotInitialized;  // mlp_scratch_setup has not run on this device
+  const size_t np = (size_t)mlp_param_count(nin, nout);
+  float* partial = base;                                       // 64 x np floats at most
+  float* delta = base + 64 * np;                               // n x 2H floats
+  return backward_kernels(params, x, act, dy, n, nin, nout, dparams, delta, partial, s);
 }
 
 hipError_t launch_mlp_adam(float* params, const float* g, float* m, float* v, int np, int step, float lr, float b1,

@@ -45,6 +45,13 @@ hipError_t launch_mlp_loss_grad(const float* y, const float* t, long long n, int
                                 MlpWork* w, hipStream_t s);
 hipError_t launch_mlp_backward(const float* params, const float* x, const float* act, const float* dy, long long n,
                                int nin, int nout, float* dparams, MlpWork* w, hipStream_t s);
+// Allocation-free form of launch_mlp_backward: the work memory is a static device array of 4 MiB
+// (one per GPU, shared by every call on it); n <= mlp_noalloc_max_samples(nin, nout).
+// mlp_scratch_setup() must have run once on the current device (vps_create does it).
+hipError_t mlp_scratch_setup();
+long long mlp_noalloc_max_samples(int nin, int nout);
+hipError_t launch_mlp_backward_noalloc(const float* params, const float* x, const float* act, const float* dy,
+                                       long long n, int nin, int nout, float* dparams, hipStream_t s);
 hipError_t launch_mlp_adam(float* params, const float* g, float* m, float* v, int np, int step, float lr, float b1,
                            float b2, float eps, hipStream_t s);
 // features -> MLP -> clamp(exp(y), 1/4, 4) per patch of a level, fallback 1 on non-finite output.

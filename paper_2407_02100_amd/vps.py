@@ -93,6 +93,7 @@ SIGNATURES = {
     "vps_mlp_forward": (_i, [_vp, _vp, _vp, _ll, _vp, _vp]),
     "vps_mlp_loss_grad": (_i, [_vp, _vp, _vp, _ll, _vp, _vp]),
     "vps_mlp_backward": (_i, [_vp, _vp, _vp, _vp, _vp, _ll, _vp]),
+    "vps_mlp_backward_noalloc": (_i, [_vp, _vp, _vp, _vp, _vp, _ll, _vp]),
     "vps_mlp_adam": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _f, _f, _f, _f]),
     "vps_mlp_infer_patches": (_i, [_vp, _i, _vp, ctypes.POINTER(_ll)]),
     "vps_timing_enable": (_i, [_vp, _i]),
@@ -388,6 +389,15 @@ class Context:
         self._check(lib().vps_mlp_backward(self.h, _ptr(params), _ptr(x), _ptr(act), _ptr(dy), x.shape[0],
                                            _ptr(dparams)), "vps_mlp_backward")
 
+    def mlp_backward_noalloc(self, params, x, act, dy, dparams):
+        n = x.shape[0]
+        _check_args("vps_mlp_backward_noalloc", [("params", params, "f32", self._nparams),
+                                                 ("x", x, "f32", n * self._nin), ("act", act, "f32", n * 2 * 64),
+                                                 ("dy", dy, "f32", n * self._nout),
+                                                 ("dparams", dparams, "f32", self._nparams)])
+        self._check(lib().vps_mlp_backward_noalloc(self.h, _ptr(params), _ptr(x), _ptr(act), _ptr(dy), n,
+                                                   _ptr(dparams)), "vps_mlp_backward_noalloc")
+
     def mlp_adam(self, params, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         P = self._nparams
         _check_args("vps_mlp_adam", [("params", params, "f32", P), ("g", g, "f32", P), ("m", m, "f32", P),
@@ -435,7 +445,7 @@ for _n in ("destroy", "set_stream", "level_nodes", "level_cells", "level_patches
            "set_patch_scaling", "apply", "residual", "restrict", "prolongate_add", "coarse_solve",
            "smooth_color", "smooth", "vcycle", "solve", "vcycle_iterate", "patch_features", "patch_rho8",
            "rho8_features", "patch_targets",
-           "mlp_forward", "mlp_loss_grad", "mlp_backward", "mlp_adam", "mlp_infer_patches", "timing_enable",
+           "mlp_forward", "mlp_loss_grad", "mlp_backward", "mlp_backward_noalloc", "mlp_adam", "mlp_infer_patches", "timing_enable",
            "timing_get", "sync"):
     globals()["vps_" + _n] = _method_alias(_n)
 
