@@ -190,3 +190,41 @@ def test_learned_and_plain_solve_varcoef(vps):
         assert info["rel_residual_true"] <= 1e-10 and res <= 1e-10, mode
     assert out["learned"][0]["iterations"] <= out["mean"][0]["iterations"] + 1
     assert np.linalg.norm(out["learned"][1] - out["mean"][1]) <= 1e-7 * np.linalg.norm(out["mean"][1])
+
+
+def test_fp64_sweep_all_colors_full_size(vps):
+    """One FP64 sweep at 513^3 in the bench's kernel choice (automatic: a row of seven patches per wave),
+    color by color: each color's update of 40 sampled patches against the oracle's exact local solve from the
+    GPU's state before that color, to the stated FP64 sweep tolerance, ||u_gpu - u_oracle||_2 <=
+    1e-12 ||u_oracle||_2 over the sampled interiors (and 1e-11 per patch in the max norm)."""
+    import torch
+    k, N = K5, N5
+    u0 = vi.seeded_vector(3, k, N, 107)
+    b = vi.seeded_vector(3, k, N, 7)
+    h = 1.0 / N
+    Abar = smoother.patch_closure_operator(3, k, h)
+    ipos = smoother.closure_interior_positions(3, k)
+    gpos = np.setdiff1d(np.arange(Abar.shape[0]), ipos)
+    cho = sla.cho_factor(Abar[np.ix_(ipos, ipos)])
+    Aig = Abar[np.ix_(ipos, gpos)]
+    with vps.Context(3, k, N, 1, vcycle_dtype="f64") as ctx:
+        u, bd = dev(u0), dev(b)
+        prev = u0
+        for color in range(8):
+            say("full-size FP64 sweep, color", color)
+            ctx.smooth_color(0, u, bd, color)
+            cur = host(u)
+            mask = _color_interior_mask(3, k, N, color)
+            assert np.array_equal(cur[~mask], prev[~mask])
+            num = den = 0.0
+            for v in _sample_vertices(N, color, 40, 31 + color):
+                clo = mesh.patch_closure(3, k, N, v)
+                inner = clo[ipos]
+                want = sla.cho_solve(cho, b[inner] - Aig @ prev[clo[gpos]])
+                got = cur[inner]
+                assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max(), (color, v)
+                num += float(np.sum((got - want) ** 2))
+                den += float(np.sum(want ** 2))
+            say("  relative 2-norm error over the sampled interiors", (num / den) ** 0.5)
+            assert (num / den) ** 0.5 <= 1e-12, color
+            prev = cur
