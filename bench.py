@@ -132,7 +132,7 @@ def _median3(fn, reps=3):
         t0 = time.perf_counter()
         out = fn()
         ts.append(time.perf_counter() - t0)
-    return sorted(ts)[1], out
+    return sorted(ts)[len(ts) // 2], out
 
 
 def oracle_child(n_cells: int, degree: int, dim: int, budget_s: float):
@@ -353,7 +353,7 @@ def run_extras(torch, vps, vi):
         res[tag] = {"targets_and_dataset_s": t1 - t0, "train_s": hist["seconds"], "train_samples": hist["train_samples"],
                     "val_loss_plain": learned.baseline_loss(T[: hist["val_samples"]]),
                     "val_loss_learned": hist["val_loss"][-1], "plain": cmp["mean"], "learned": cmp["learned"],
-                    "exact_targets": cmp["exact"],
+                    "exact_targets": cmp["exact"], "exact_local_solver": cmp["exact_solver"],
                     "speedup_learned_vs_plain": (cmp["mean"]["seconds"] / cmp["learned"]["seconds"]
                                                  if cmp["mean"]["status"] == 0 else None)}
     out["varcoef3d_q2_n64"] = res

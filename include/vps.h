@@ -64,7 +64,12 @@ typedef enum { VPS_F64 = 0, VPS_F32 = 1 } vps_dtype;
 typedef enum {
   VPS_COEF_CONST = 0,          /* rho = 1: exact FDM local solver */
   VPS_COEF_CELL_MEAN_FDM = 1,  /* rho per cell: residual with rho, FDM with patch mean of rho */
-  VPS_COEF_CELL_LEARNED = 2    /* as 1, each FDM eigenmode scaled by a per-patch factor */
+  VPS_COEF_CELL_LEARNED = 2,   /* as 1, each FDM eigenmode scaled by a per-patch factor */
+  VPS_COEF_CELL_EXACT = 3      /* rho per cell, exact dense local solvers A_j(rho)^{-1} (eq:main:2),
+                                  formed by vps_set_coefficient: the ceiling for any per-patch
+                                  correction of the FDM inverse; Q2, 3D, FP64 V-cycle, whole
+                                  colors (per color: the global residual, then the dense patch
+                                  solves), 5.8 KB of device memory per patch */
 } vps_coef;
 
 /* Smoother algorithm: the two colorized forms of Section 3.2. */
@@ -179,7 +184,8 @@ long long vps_level_patches(const vps_context* ctx, int level);
 
 /* Per-cell coefficient rho on the finest level: N^d FP64 values on the
  * device, cells lexicographic (x fastest), all > 0.  Coarser levels get the
- * mean of the 2^d children.  Only for coef != VPS_COEF_CONST.  Rebuilds the
+ * mean of the 2^d children.  Only for coef != VPS_COEF_CONST.  With
+ * VPS_COEF_CELL_EXACT it also forms every level's dense local inverses.  Rebuilds the
  * dense coarse solver (host FP64 Cholesky inverse of the coarsest operator,
  * at most 4096 free nodes).  Synchronises. */
 vps_status vps_set_coefficient(vps_context* ctx, const double* rho_cells_dev);

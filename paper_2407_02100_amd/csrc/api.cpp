@@ -31,6 +31,7 @@ struct Level {
   double* rho64 = nullptr;  // per-cell coefficient
   float* rho32 = nullptr;
   float* scal = nullptr;    // learned per-patch eigenmode factors
+  double* binv = nullptr;   // exact local solvers: per patch A_j(rho)^{-1}, 27 x 27 FP64 (Q2, 3D)
   // 2-cell patch: interior rows (q x p) of mass/stiffness; halves per cell
   Mat Mfull, Kfull, Mh[2], Kh[2];
   Mat T1;                   // FDM eigenvectors (q x q)
@@ -427,6 +428,13 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   P.Te = L.Te.empty() ? nullptr : L.Te.data();
   P.To = L.Te.empty() ? nullptr : L.To.data();
   P.lam_int = L.lam_int.empty() ? nullptr : L.lam_int.data();
+  if (coef == VPS_COEF_CELL_EXACT) {
+    // exact dense local solvers (the ceiling of any per-patch correction of the FDM inverse):
+    // the global residual of the current iterate, then u_I += A_j(rho)^{-1} r_I on the color
+    hipError_t e = do_operator(c, l, u, b, L.sep_r, t);
+    if (e != hipSuccess) return e;
+    return vps::launch_exact_apply((double*)u, (const double*)L.sep_r, L.binv, L.n1, L.ncell, color, c->stream);
+  }
   if (c->cfg.algorithm == VPS_ALG_SEPARATED) {
     // Algorithm 3: global residual, then the local solves of the color's patches
     hipError_t e = do_operator(c, l, u, b, L.sep_r, t);
@@ -725,6 +733,7 @@ void free_all(vps_context* c) {
     hipFree(L.rho64);
     hipFree(L.rho32);
     hipFree(L.scal);
+    hipFree(L.binv);
   }
   for (int i = 0; i < 2; ++i) {
     hipFree(c->cT0[i]);
@@ -769,10 +778,16 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (n0 < 2) return VPS_E_UNSUPPORTED;
   if (C.pre_sweeps < 0 || C.post_sweeps < 0) return VPS_E_ARG;
   if (C.vcycle_dtype != VPS_F64 && C.vcycle_dtype != VPS_F32) return VPS_E_ARG;
-  if (C.coef < VPS_COEF_CONST || C.coef > VPS_COEF_CELL_LEARNED) return VPS_E_ARG;
+  if (C.coef < VPS_COEF_CONST || C.coef > VPS_COEF_CELL_EXACT) return VPS_E_ARG;
+  // dense exact local solvers: Q2 in 3D, FP64, whole colors (each color step: the global
+  // residual, then the dense patch solves)
+  if (C.coef == VPS_COEF_CELL_EXACT &&
+      (C.dim != 3 || C.degree != 2 || C.vcycle_dtype != VPS_F64 || C.algorithm != VPS_ALG_COMBINED ||
+       C.batch_layers != 0 || C.patches_per_block != 0))
+    return VPS_E_UNSUPPORTED;
   if (C.patches_per_block != 0 && !vps::valid_patches_per_block(C.patches_per_block)) return VPS_E_UNSUPPORTED;
   if (C.patches_per_block != 0 && C.dim >= 2 && C.dim <= 3 && C.degree >= 1 && C.degree <= 5 &&
-      C.coef >= VPS_COEF_CONST && C.coef <= VPS_COEF_CELL_LEARNED &&
+      C.coef >= VPS_COEF_CONST && C.coef <= VPS_COEF_CELL_EXACT &&
       !vps::patches_per_block_fits(C.degree, C.dim, C.coef, C.patches_per_block, C.vcycle_dtype == VPS_F64))
     return VPS_E_UNSUPPORTED;  // that batch of patches exceeds the workgroup LDS
   if (C.stream_min_cells < 0) return VPS_E_ARG;
@@ -834,6 +849,10 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
       for (int e = 0; e < C.dim; ++e) cells *= (size_t)L.ncell;
       if (chk(hipMalloc(&L.rho64, cells * sizeof(double)), "hipMalloc")) return bail(VPS_E_NOMEM);
       if (chk(hipMalloc(&L.rho32, cells * sizeof(float)), "hipMalloc")) return bail(VPS_E_NOMEM);
+    }
+    if (C.coef == VPS_COEF_CELL_EXACT && L.npatch > 0) {
+      if (chk(hipMalloc(&L.binv, (size_t)L.npatch * 27 * 27 * sizeof(double)), "hipMalloc")) return bail(VPS_E_NOMEM);
+      if (chk(hipMalloc(&L.sep_r, L.nodes * sizeof(double)), "hipMalloc")) return bail(VPS_E_NOMEM);
     }
     if (C.coef == VPS_COEF_CELL_LEARNED) {
       const size_t n = (size_t)L.npatch * ipow(2 * C.degree - 1, C.dim);
@@ -912,6 +931,11 @@ vps_status vps_set_coefficient(vps_context* c, const double* rho) {
     VPS_HIP(c, vps::launch_coarsen_rho(c->lv[l + 1].rho64, c->lv[l].rho64, c->lv[l].ncell, d, c->stream));
   for (int l = 0; l <= L; ++l)
     VPS_HIP(c, (vps::launch_cast<double, float>(c->lv[l].rho64, c->lv[l].rho32, cells(l), c->stream)));
+  if (c->cfg.coef == VPS_COEF_CELL_EXACT)
+    for (int l = 0; l <= L; ++l)
+      if (c->lv[l].binv)
+        VPS_HIP(c, vps::launch_exact_inverses(c->lv[l].rho64, c->lv[l].ncell, c->lv[l].Mh, c->lv[l].Kh, c->lv[l].binv,
+                                              c->stream));
   // dense coarse operator on the free nodes, FP64 on the host
   const Level& L0 = c->lv[0];
   std::vector<double> rho0(cells(0));

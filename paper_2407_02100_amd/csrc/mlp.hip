@@ -381,6 +381,114 @@ __global__ void __launch_bounds__(64) targets_kernel(const TargetArgs a, const d
   }
 }
 
+// Exact dense local solver of a Q2 patch (3D): B_j = A_j(rho)^{-1}, A_j the
+// interior block of the sum over the patch's 8 cells of rho_c times the cell's
+// Kronecker sum (eq:main:2 with the exact inverse).  One wave per patch:
+// assemble A_j in LDS, Cholesky A_j = L L^T (lane 0 the pivots, the column in
+// parallel), then lane i < 27 solves L L^T x = e_i for column i of B_j.
+// binv: npatch x 27 x 27 FP64, patch-major (B_j symmetric, so either index
+// order).
+struct ExactArgs {
+  double Mi[2][9];  // interior 3 x 3 block of the cell-h half of the level's 1D patch mass matrix
+  double Ki[2][9];
+};
+
+__global__ void __launch_bounds__(64) exact_inverse_kernel(const ExactArgs a, const double* __restrict__ rho, int ncell,
+                                                           double* __restrict__ binv) {
+  constexpr int Q = 3, N = 27;
+  __shared__ double A[N * N];
+  __shared__ double r8[8];
+  const long long j = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (lane < 8) {
+    int v[3];
+    patch_vertex(j, ncell, 3, v);
+    r8[lane] = patch_cell_rho(rho, ncell, 3, v, lane);
+  }
+  __syncthreads();
+  for (int e = lane; e < N * N; e += 64) {
+    const int o = e / N, i = e % N;
+    const int ox = o % Q, oy = (o / Q) % Q, oz = o / (Q * Q);
+    const int ix = i % Q, iy = (i / Q) % Q, iz = i / (Q * Q);
+    double v = 0.0;
+    for (int c = 0; c < 8; ++c) {
+      const int hx = c & 1, hy = (c >> 1) & 1, hz = (c >> 2) & 1;
+      const double mx = a.Mi[hx][ox * Q + ix], my = a.Mi[hy][oy * Q + iy], mz = a.Mi[hz][oz * Q + iz];
+      const double kx = a.Ki[hx][ox * Q + ix], ky = a.Ki[hy][oy * Q + iy], kz = a.Ki[hz][oz * Q + iz];
+      v += r8[c] * (kx * my * mz + mx * ky * mz + mx * my * kz);
+    }
+    A[e] = v;
+  }
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {  // lower triangle of A <- L
+    if (lane == 0) {
+      double d = A[k * N + k];
+      for (int p = 0; p < k; ++p) d -= A[k * N + p] * A[k * N + p];
+      A[k * N + k] = sqrt(d);
+    }
+    __syncthreads();
+    const int i = k + 1 + lane;
+    if (i < N) {
+      double s = A[i * N + k];
+      for (int p = 0; p < k; ++p) s -= A[i * N + p] * A[k * N + p];
+      A[i * N + k] = s / A[k * N + k];
+    }
+    __syncthreads();
+  }
+  if (lane < N) {
+    double x[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {  // L y = e_lane
+      double s = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+      for (int p = 0; p < i; ++p) s -= A[i * N + p] * x[p];
+      x[i] = s / A[i * N + i];
+    }
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {  // L^T x = y
+      double s = x[i];
+#pragma unroll
+      for (int p = i + 1; p < N; ++p) s -= A[p * N + i] * x[p];
+      x[i] = s / A[i * N + i];
+    }
+    double* out = binv + j * (N * N) + lane;
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i * N] = x[i];  // column lane of B_j: B[i][lane]
+  }
+}
+
+// One color step of the exact local solver: u_I += B_j r_I for every patch of
+// the color (r = b - A u of the current iterate, computed before the step; the
+// color's patches do not read each other's writes).  One wave per patch.
+__global__ void __launch_bounds__(64) exact_apply_kernel(double* __restrict__ u, const double* __restrict__ r,
+                                                         const double* __restrict__ binv, int n1, int ncell, int v0x,
+                                                         int v0y, int v0z, int npx, int npy, long long ncolor) {
+  constexpr int Q = 3, N = 27;
+  __shared__ double rs[N];
+  const long long t = blockIdx.x;
+  if (t >= ncolor) return;
+  const int lane = threadIdx.x;
+  const int px = (int)(t % npx), py = (int)((t / npx) % npy), pz = (int)(t / ((long long)npx * npy));
+  const int vx = v0x + 2 * px, vy = v0y + 2 * py, vz = v0z + 2 * pz;
+  const long long m = ncell - 1;
+  const long long j = (long long)(vx - 1) + m * ((long long)(vy - 1) + m * (long long)(vz - 1));
+  size_t node = 0;
+  if (lane < N) {
+    const int ix = lane % Q, iy = (lane / Q) % Q, iz = lane / (Q * Q);
+    node = (size_t)(2 * (vx - 1) + 1 + ix) + (size_t)n1 * ((size_t)(2 * (vy - 1) + 1 + iy) +
+                                                         (size_t)n1 * (size_t)(2 * (vz - 1) + 1 + iz));
+    rs[lane] = r[node];
+  }
+  __syncthreads();
+  if (lane < N) {
+    const double* B = binv + j * (N * N);
+    double d = 0.0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) d += B[q * N + lane] * rs[q];
+    u[node] += d;
+  }
+}
+
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 // Grow a work buffer; waits for the stream first so that no queued kernel
@@ -461,6 +569,37 @@ hipError_t launch_patch_targets(const double* rho8, long long n, const std::vect
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_exact_inverses(const double* rho, int ncell, const std::vector<double>* Mh,
+                                 const std::vector<double>* Kh, double* binv, hipStream_t s) {
+  constexpr int Q = 3, P = 5;
+  ExactArgs a;
+  for (int h = 0; h < 2; ++h)
+    for (int o = 0; o < Q; ++o)
+      for (int i = 0; i < Q; ++i) {
+        a.Mi[h][o * Q + i] = Mh[h][o * P + i + 1];
+        a.Ki[h][o * Q + i] = Kh[h][o * P + i + 1];
+      }
+  const long long np = (long long)(ncell - 1) * (ncell - 1) * (ncell - 1);
+  if (np <= 0) return hipSuccess;
+  if (np >= (1LL << 31)) return hipErrorInvalidValue;
+  exact_inverse_kernel<<<(unsigned)np, 64, 0, s>>>(a, rho, ncell, binv);
+  return hipGetLastError();
+}
+
+hipError_t launch_exact_apply(double* u, const double* r, const double* binv, int n1, int ncell, int color,
+                              hipStream_t s) {
+  int v0[3], np[3];
+  for (int e = 0; e < 3; ++e) {
+    v0[e] = ((color >> e) & 1) ? 1 : 2;
+    np[e] = (v0[e] <= ncell - 1) ? (ncell - 1 - v0[e]) / 2 + 1 : 0;
+    if (np[e] == 0) return hipSuccess;
+  }
+  const long long nc = (long long)np[0] * np[1] * np[2];
+  if (nc >= (1LL << 31)) return hipErrorInvalidValue;
+  exact_apply_kernel<<<(unsigned)nc, 64, 0, s>>>(u, r, binv, n1, ncell, v0[0], v0[1], v0[2], np[0], np[1], nc);
+  return hipGetLastError();
 }
 
 hipError_t launch_mlp_forward(const float* params, const float* x, long long n, int nin, int nout, float* y,

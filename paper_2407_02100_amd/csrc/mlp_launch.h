@@ -39,6 +39,13 @@ hipError_t launch_patch_targets(const double* rho8, long long n, const std::vect
                                 const std::vector<double>* Kh, const double* T1, const double* lam, double* cstar,
                                 float* log_target, hipStream_t s);
 
+// Exact dense local solvers of Q2 patches (3D): binv[j] = A_j(rho)^{-1} for every patch of a level
+// (npatch x 27 x 27 FP64), from the level's half-cell 1D matrices; and one color step u_I += B_j r_I.
+hipError_t launch_exact_inverses(const double* rho, int ncell, const std::vector<double>* Mh,
+                                 const std::vector<double>* Kh, double* binv, hipStream_t s);
+hipError_t launch_exact_apply(double* u, const double* r, const double* binv, int n1, int ncell, int color,
+                              hipStream_t s);
+
 hipError_t launch_mlp_forward(const float* params, const float* x, long long n, int nin, int nout, float* y,
                               float* act, hipStream_t s);
 hipError_t launch_mlp_loss_grad(const float* y, const float* t, long long n, int nout, float* dy, float* loss,

@@ -173,15 +173,17 @@ def apply_exact_targets(ctx):
 
 def compare(params, n_cells: int = 64, levels: int = 5, rho_seed: int = 4, rhs_seed: int = 4, rtol: float = 1e-10,
             maxit: int = 300, corr_len: float = 1.0 / 8.0, iters: int = 12, exact: bool = True):
-    """Plain rhobar-FDM vs learned scaling (and, with exact=True, the exact targets the network is
-    trained on) on one field: convergence factor and time to rtol."""
+    """Plain rhobar-FDM vs learned scaling on one field: convergence factor and time to rtol.  With
+    exact=True also the exact targets the network is trained on ('exact': a perfect network) and the exact
+    dense local solvers A_j(rho)^{-1} ('exact_solver': the ceiling of any per-patch correction)."""
     import torch
     import vps_inputs as vi
     rho = torch.from_numpy(vi.rho_cells(n_cells, rho_seed, corr_len=corr_len)).to("cuda")
     b = torch.from_numpy(vi.seeded_vector(3, 2, n_cells, rhs_seed)).to("cuda")
     out = {}
-    for mode in ("mean", "learned") + (("exact",) if exact else ()):
-        with vps.Context(3, 2, n_cells, levels, coef="learned" if mode == "exact" else mode) as ctx:
+    coefs = {"mean": "mean", "learned": "learned", "exact": "learned", "exact_solver": "exact"}
+    for mode in ("mean", "learned") + (("exact", "exact_solver") if exact else ()):
+        with vps.Context(3, 2, n_cells, levels, coef=coefs[mode]) as ctx:
             ctx.set_coefficient(rho)
             if mode == "learned":
                 fb = apply_scaling(ctx, params)

@@ -19,9 +19,10 @@ LIB_PATH = os.path.join(HERE, "libvps.so")
 VPS_OK, VPS_E_ARG, VPS_E_UNSUPPORTED, VPS_E_HIP = 0, -1, -2, -3
 VPS_E_NOMEM, VPS_E_NOT_CONVERGED, VPS_E_NONFINITE, VPS_E_STATE = -4, -5, -6, -7
 VPS_F64, VPS_F32 = 0, 1
-VPS_COEF_CONST, VPS_COEF_CELL_MEAN_FDM, VPS_COEF_CELL_LEARNED = 0, 1, 2
+VPS_COEF_CONST, VPS_COEF_CELL_MEAN_FDM, VPS_COEF_CELL_LEARNED, VPS_COEF_CELL_EXACT = 0, 1, 2, 3
 
-_COEF = {"const": VPS_COEF_CONST, "mean": VPS_COEF_CELL_MEAN_FDM, "learned": VPS_COEF_CELL_LEARNED}
+_COEF = {"const": VPS_COEF_CONST, "mean": VPS_COEF_CELL_MEAN_FDM, "learned": VPS_COEF_CELL_LEARNED,
+         "exact": VPS_COEF_CELL_EXACT}
 _ALGORITHM = {"combined": 0, "separated": 1}
 _DTYPE = {"f64": VPS_F64, "f32": VPS_F32}
 

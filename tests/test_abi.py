@@ -75,10 +75,16 @@ def test_status_strings(lib):
     (dict(dim=2, degree=2, n_cells=8, n_levels=2, patches_per_wave=3), -2),   # rows of patches: 3D only
     (dict(dim=3, degree=5, n_cells=8, n_levels=2, patches_per_wave=3), -2),   # rows of patches: degree 2..4
     (dict(dim=3, degree=3, n_cells=8, n_levels=2, patches_per_wave=3, patch_order=3), -2),
+    (dict(dim=3, degree=2, n_cells=8, n_levels=2, coef=4), -1),
+    (dict(dim=2, degree=2, n_cells=8, n_levels=2, coef=3), -2),   # exact local solvers: Q2 in 3D only
+    (dict(dim=3, degree=3, n_cells=8, n_levels=2, coef=3), -2),
+    (dict(dim=3, degree=2, n_cells=8, n_levels=2, coef=3, vcycle=1), -2),   # ... FP64 only
+    (dict(dim=3, degree=2, n_cells=8, n_levels=2, coef=3, batch_layers=2), -2),
 ])
 def test_create_rejects_invalid_configurations(lib, cfg, status):
     from paper_2407_02100_amd import vps
-    c = vps.vps_config(cfg["dim"], cfg["degree"], cfg["n_cells"], cfg["n_levels"], cfg.get("pre", 1), 1, 0, 0,
+    c = vps.vps_config(cfg["dim"], cfg["degree"], cfg["n_cells"], cfg["n_levels"], cfg.get("pre", 1), 1,
+                       cfg.get("vcycle", 0), cfg.get("coef", 0),
                        cfg.get("patches_per_block", 0), cfg.get("stream_min_cells", 0), cfg.get("algorithm", 0),
                        cfg.get("patch_order", 0), cfg.get("batch_layers", 0), cfg.get("patches_per_wave", 0),
                        cfg.get("vcycle_graph", 0), cfg.get("wave_rows_2d", 0))

@@ -96,3 +96,12 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode != 0
     assert "--gpus 1" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_median_helper_handles_one_and_three_runs():
+    import bench
+    calls = []
+    t, out = bench._median3(lambda: calls.append(1) or len(calls), 1)
+    assert out == 1 and len(calls) == 1 and t >= 0.0
+    t, out = bench._median3(lambda: calls.append(1) or len(calls))
+    assert out == 4 and len(calls) == 4
