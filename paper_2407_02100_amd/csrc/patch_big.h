@@ -14,8 +14,10 @@ namespace vps {
 // with every stage that has more lines than lanes run in passes of 64.  The
 // residual contracts z, x, y (the last in lanes (z, x) over y), so the
 // right-hand side is loaded straight into the lanes that subtract it and
-// needs no LDS, which keeps the LDS at 2 (2K-1)(2K+1)^2 + 2 (2K-1)^2 (2K+1)
-// values.
+// needs no LDS; the x contraction writes its outputs over its own inputs
+// (each lane owns one (z, y) line of both arrays), which keeps the LDS at
+// 2 (2K-1)(2K+1)^2 values (17.4 KB in FP64 at K = 5: 9 waves per CU fit, the
+// registers allow 8).
 //
 // Stages:  0. every global load (boundary columns along z, the two end values
 // of the interior columns, the right-hand side rows);  1. z contraction;
@@ -52,8 +54,8 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
   constexpr int NL = (Q2 + 63) / 64;     // passes over the Q^2 lines
   constexpr int NX = (Q * P + 63) / 64;  // passes over the Q P lines of the x contraction
   static_assert(NB <= 64, "the boundary columns must fit one wave");
-  __shared__ T Z[2 * Q * P2];      // [t][oz][y][x] after the z contraction; later the FDM buffers
-  __shared__ T AE[2 * Q * P * Q];  // [t][oz][y][ox] after the x contraction
+  __shared__ T Z[2 * Q * P2];  // [t][oz][y][x] after the z contraction, [t][oz][y][ox] (ox < Q) after the
+                               // x contraction (in place); later the FDM buffers
   __shared__ BigFdm<T, K> FS;
   T* W0 = Z;
   T* W1 = Z + Q3;
@@ -169,14 +171,17 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
           ev = fma(sym_k(a.band, j, x), zm[x], ev);
           ev = fma(sym_m(a.band, j, x), zk[x], ev);
         }
-        AE[((0 * Q + oz) * P + y) * Q + o] = av;
-        AE[((1 * Q + oz) * P + y) * Q + o] = ev;
+        Z[(0 * Q + oz) * P2 + y * P + o] = av;  // over this lane's own line (read above)
+        Z[(1 * Q + oz) * P2 + y * P + o] = ev;
       }
     }
   }
   __syncthreads();
 
-  // ---- 3. y contraction, local residual, T^T along y  (lines (oz, ox)) ----
+  // ---- 3. y contraction, local residual, T^T along y  (lines (oz, ox)); the
+  //      results wait in registers until every lane has read its inputs, which
+  //      lie where W0 goes ----
+  T mres[NL][Q];
 #pragma unroll
   for (int s = 0; s < NL; ++s) {
     const int i = lane + 64 * s;
@@ -185,10 +190,10 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
       T av[P], ev[P];
 #pragma unroll
       for (int y = 0; y < P; ++y) {
-        av[y] = AE[((0 * Q + oz) * P + y) * Q + ox];
-        ev[y] = AE[((1 * Q + oz) * P + y) * Q + ox];
+        av[y] = Z[(0 * Q + oz) * P2 + y * P + ox];
+        ev[y] = Z[(1 * Q + oz) * P2 + y * P + ox];
       }
-      T r[Q], m[Q];
+      T r[Q];
 #pragma unroll
       for (int o = 0; o < Q; ++o) {
         const int j = o + 1;
@@ -201,9 +206,17 @@ __global__ void __launch_bounds__(64) patch_big3_kernel(const BigArgs<T, K> a) {
         }
         r[o] = bv[s][o] - acc;
       }
-      fdm_forward<T, K>(FS.f, r, m);
+      fdm_forward<T, K>(FS.f, r, mres[s]);
+    }
+  }
+  __syncthreads();
 #pragma unroll
-      for (int q = 0; q < Q; ++q) W0[(oz * Q + q) * Q + ox] = m[q];
+  for (int s = 0; s < NL; ++s) {
+    const int i = lane + 64 * s;
+    if (i < Q2) {
+      const int oz = i / Q, ox = i % Q;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) W0[(oz * Q + q) * Q + ox] = mres[s][q];
     }
   }
   __syncthreads();

@@ -70,7 +70,7 @@ hipError_t go_stream(const StreamLaunch& L, hipStream_t s) {
 
 template <typename T, int K>
 hipError_t launch_stream_operator(const StreamLaunch& L, hipStream_t s) {
-  return go_stream<T, STREAM_OPERATOR, K>(L, s);
+  return L.b ? go_stream<T, STREAM_RESIDUAL, K>(L, s) : go_stream<T, STREAM_OPERATOR, K>(L, s);
 }
 template <typename T, int K>
 hipError_t launch_stream_restrict(const StreamLaunch& L, hipStream_t s) {

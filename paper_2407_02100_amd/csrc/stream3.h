@@ -31,7 +31,9 @@
 
 namespace vps {
 
-enum StreamKind { STREAM_OPERATOR = 0, STREAM_RESTRICT = 1, STREAM_PROLONG = 2 };
+// STREAM_RESIDUAL is the operator with the right-hand side subtracted (b - A u); the plain
+// operator is a kind of its own so that it holds no right-hand-side registers.
+enum StreamKind { STREAM_OPERATOR = 0, STREAM_RESTRICT = 1, STREAM_PROLONG = 2, STREAM_RESIDUAL = 3 };
 
 // Shape of one kind and degree.  In x and y a period of PO outputs reads a
 // window of W inputs starting PI inputs after the previous period's.  TX, TY
@@ -41,7 +43,8 @@ enum StreamKind { STREAM_OPERATOR = 0, STREAM_RESTRICT = 1, STREAM_PROLONG = 2 }
 // ZO output planes accumulated per z cell.
 template <int KIND, int K>
 struct StreamShape {
-  static constexpr bool OP = KIND == STREAM_OPERATOR;
+  static constexpr bool RES = KIND == STREAM_RESIDUAL;
+  static constexpr bool OP = KIND == STREAM_OPERATOR || RES;
   static constexpr bool PR = KIND == STREAM_PROLONG;
   static constexpr int PO = PR ? 2 * K : K;
   static constexpr int PI = (KIND == STREAM_RESTRICT) ? 2 * K : K;
@@ -80,7 +83,7 @@ struct StreamArgs {
   using S = StreamShape<KIND, K>;
   static constexpr int NS = (K + 1) * (K + 2) / 2;
   const T* __restrict__ in;
-  const T* __restrict__ b;  // operator only: out = b - A u if non-null
+  const T* __restrict__ b;  // residual only: out = b - A u
   T* __restrict__ out;
   int n1_in, n1_out;
   int ncz;                  // cells of the output grid per direction
@@ -180,13 +183,14 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
 
   // prefetch registers: the next input plane's tile elements (and b of the next plane for the residual)
   T pf[NPF];
-  T pb[NIT][PO];
+  constexpr int NB = S::RES ? NIT : 1, PB = S::RES ? PO : 1;
+  T pb[NB][PB];
   auto prefetch = [&](int p) {
     const T* src = a.in + (size_t)p * pin;
 #pragma unroll
     for (int m = 0; m < NPF; ++m) pf[m] = ld_or_zero(src, pf_off[m], pf_ok[m]);
-    if constexpr (OP) {
-      if (a.b != nullptr) {
+    if constexpr (S::RES) {
+      {
         const T* bs = a.b + (size_t)p * pout;
 #pragma unroll
         for (int m = 0; m < NIT; ++m)
@@ -202,12 +206,12 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
 
   // x-y contraction of the plane held in pf; the next plane's loads are issued first.
   // Results: v0 (operator: mm = My Mx u; restriction: Ry Rx r), v1 (operator: s).
-  T v0[NIT][PO], v1[NIT][PO], cb[NIT][PO];
+  T v0[NIT][PO], v1[NIT][PO], cb[NB][PB];
   auto plane = [&](int p, int plast) {
 #pragma unroll
     for (int m = 0; m < NPF; ++m)
       if (t + kBlock * m < NIX * NIY) U[t + kBlock * m] = pf[m];
-    if constexpr (OP) {
+    if constexpr (S::RES) {
 #pragma unroll
       for (int m = 0; m < NIT; ++m)
 #pragma unroll
@@ -302,7 +306,7 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
     }
   };
 
-  const bool resid = OP && a.b != nullptr;
+  constexpr bool resid = S::RES;
   if constexpr (OP) {
     // planes K*cs .. K*cz1; the vertex plane of each cell is folded into both of its cells
     const int plast = K * cz1;
@@ -329,7 +333,7 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
           for (int i = 0; i <= K; ++i)
             acc[m][j][i] = fma(a.z(1, i, 0), pm[m][j], a.z(0, i, 0) * ps[m][j]);
           acc[m][j][0] += carry;
-          if (resid) acc[m][j][0] -= cb[m][j];
+          if constexpr (resid) acc[m][j][0] -= cb[m][j];
         }
 #pragma unroll
       for (int l = 1; l <= K; ++l) {
@@ -341,7 +345,9 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
 #pragma unroll
             for (int i = 0; i <= K; ++i)
               acc[m][j][i] = fma(a.z(1, i, l), v0[m][j], fma(a.z(0, i, l), v1[m][j], acc[m][j][i]));
-            if (resid && l < K) acc[m][j][l] -= cb[m][j];
+            if constexpr (resid) {
+              if (l < K) acc[m][j][l] -= cb[m][j];
+            }
           }
       }
       // the vertex plane K*(c+1) also starts cell c+1
@@ -353,7 +359,7 @@ __global__ void __launch_bounds__(kBlock) stream3_kernel(const StreamArgs<T, KIN
           ps[m][j] = v1[m][j];
         }
       if (c >= cz0) {
-        if (resid) {
+        if constexpr (resid) {
 #pragma unroll
           for (int m = 0; m < NIT; ++m)
 #pragma unroll
