@@ -60,9 +60,15 @@ struct Row3Shape {
   static constexpr int GQ = G * Q;     // interior columns (and x rows) of the G patches
   static constexpr int F = G + 2;                 // x-face columns of the G patches (as C)
   static constexpr bool FACE_PASS = K >= 4;        // stage P (measured faster at K = 4 only)
-  static constexpr int PLANE = 3 * Q * C;          // LDS of stages A-B: F_M, F_E, rhs rows of one plane
+  // LDS row stride of the plane buffers: odd, so that lanes (patch, oy) reading
+  // column c0 + x of row oy (c0 = 2K patch) fall into different banks
+  static constexpr int CS = C | 1;
+  static constexpr int PLANE = 3 * Q * CS;         // LDS of stages A-B: F_M, F_E, rhs rows of one plane
   static constexpr int FACE = FACE_PASS ? 2 * Q * Q * F : 0;  // LDS of stages P-B: the faces' interior share
-  static constexpr int CUBE = G * Q * Q * Q;       // LDS of stages C-D: the G interiors
+  // LDS of stages C-D: the G interiors, one patch every PS values (one more than
+  // Q^3, which spreads the lanes (patch, line) of the line-wise passes over the banks)
+  static constexpr int PS = Q * Q * Q + 1;
+  static constexpr int CUBE = G * PS;
   static constexpr int LDS = PLANE + FACE > CUBE ? PLANE + FACE : CUBE;
   static_assert(C <= 64 && GQ <= 64 && F * Q <= 64, "a row of patches must fit one wave");
   static_assert(FACE <= PLANE, "the prepass transpose (FACE values at the start) stays below the face buffer");
@@ -91,12 +97,12 @@ struct Row3Args {
 template <typename T, int K>
 __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) {
   using R = Row3Shape<K>;
-  constexpr int P = R::P, Q = R::Q, S = R::S, G = R::G, C = R::C, GQ = R::GQ, M = K - 1;
+  constexpr int P = R::P, Q = R::Q, S = R::S, G = R::G, C = R::C, CS = R::CS, PS = R::PS, GQ = R::GQ, M = K - 1;
   constexpr int F = R::F;
   __shared__ T L[R::LDS];
   T* FM = L;              // [oy][column] of the current plane
-  T* FE = L + Q * C;      // [oy][column]
-  T* BB = L + 2 * Q * C;  // [oy][column]: right-hand side of the current plane
+  T* FE = L + Q * CS;     // [oy][column]
+  T* BB = L + 2 * Q * CS; // [oy][column]: right-hand side of the current plane
   T* DM = L + R::PLANE;   // [oz][oy][face]: interior share of F_M at the x-face columns
   T* DE = DM + Q * Q * F; // [oz][oy][face]: ... of F_E
   T* ZI = L;              // stage P: [t][face][oz][y] after the z contraction (below the face buffer)
@@ -306,9 +312,9 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
             fe = fma(sym_k(a.band, jy, P - 1), c8m, fe);
             fe = fma(sym_m(a.band, jy, P - 1), c8k, fe);
           }
-          FM[oy * C + lane] = fm;
-          FE[oy * C + lane] = fe;
-          BB[oy * C + lane] = bcur[oy];
+          FM[oy * CS + lane] = fm;
+          FE[oy * CS + lane] = fe;
+          BB[oy * CS + lane] = bcur[oy];
         }
       } else {
         T zm[P], zk[P];
@@ -336,9 +342,9 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
             fe = fma(sym_k(a.band, jy, y), zm[y], fe);
             fe = fma(sym_m(a.band, jy, y), zk[y], fe);
           }
-          FM[oy * C + lane] = fm;
-          FE[oy * C + lane] = fe;
-          BB[oy * C + lane] = bcur[oy];
+          FM[oy * CS + lane] = fm;
+          FE[oy * CS + lane] = fe;
+          BB[oy * CS + lane] = bcur[oy];
         }
       }
     }
@@ -349,8 +355,8 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
       T fm[P], fe[P], r[Q];
 #pragma unroll
       for (int x = 0; x < P; ++x) {
-        fm[x] = FM[oy * C + c0 + x];
-        fe[x] = FE[oy * C + c0 + x];
+        fm[x] = FM[oy * CS + c0 + x];
+        fe[x] = FE[oy * CS + c0 + x];
       }
       if constexpr (FP) {
         fm[0] += DM[(oz * Q + oy) * F + fl];
@@ -368,7 +374,7 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
           s = fma(sym_k(a.band, jx, x), fm[x], s);
           s = fma(sym_m(a.band, jx, x), fe[x], s);
         }
-        r[ox] = BB[oy * C + c0 + 1 + ox] - s;
+        r[ox] = BB[oy * CS + c0 + 1 + ox] - s;
       }
       fdm_forward<T, K>(a.f, r, mr[oz]);
     }
@@ -385,7 +391,7 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
       for (int oz = 0; oz < Q; ++oz) v[oz] = mr[oz][mx];
       fdm_forward<T, K>(a.f, v, c);
 #pragma unroll
-      for (int mz = 0; mz < Q; ++mz) W[((pp * Q + mx) * Q + mz) * Q + oy] = c[mz];
+      for (int mz = 0; mz < Q; ++mz) W[pp * PS + (mx * Q + mz) * Q + oy] = c[mz];
     }
   }
   __syncthreads();
@@ -399,7 +405,7 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
     for (int mz = 0; mz < Q; ++mz) {
       T v[Q], c[Q];
 #pragma unroll
-      for (int oy = 0; oy < Q; ++oy) v[oy] = W[((pp * Q + mx) * Q + mz) * Q + oy];
+      for (int oy = 0; oy < Q; ++oy) v[oy] = W[pp * PS + (mx * Q + mz) * Q + oy];
       fdm_forward<T, K>(a.f, v, c);  // T^T along y
       const T s2 = lmx + a.lam[mz];
 #pragma unroll
@@ -424,7 +430,7 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
 #pragma unroll
     for (int z = 0; z < Q; ++z)
 #pragma unroll
-      for (int y = 0; y < Q; ++y) W[((pp * Q + z) * Q + y) * Q + mx] = e[z][y];
+      for (int y = 0; y < Q; ++y) W[pp * PS + (z * Q + y) * Q + mx] = e[z][y];
   }
   __syncthreads();
 
@@ -434,7 +440,7 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
     const int y = ll;
 #pragma unroll
     for (int z = 0; z < Q; ++z) {
-      T* w = W + ((pp * Q + z) * Q + y) * Q;
+      T* w = W + pp * PS + (z * Q + y) * Q;
       T c[Q], d[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) c[q] = w[q];
@@ -451,7 +457,7 @@ __global__ void __launch_bounds__(64) patch_row3_kernel(const Row3Args<T, K> a) 
     for (int z = 0; z < Q; ++z)
 #pragma unroll
       for (int y = 0; y < Q; ++y)
-        buf_store<T>(W[((pp * Q + z) * Q + y) * Q + x], ur, off2, sbase + splane * (z + 1) + srow * (y + 1));
+        buf_store<T>(W[pp * PS + (z * Q + y) * Q + x], ur, off2, sbase + splane * (z + 1) + srow * (y + 1));
   }
 }
 
