@@ -5,9 +5,10 @@ Two steps:
 1. ``python -m paper_2407_02100_amd.traffic_probe run [--dtype f32|f64] [--algorithm combined|separated]``
    runs on the GPU, under ``rocprofv3 --pmc <COUNTER> --output-format csv``:
    one plain device-to-device copy of a known size (the calibration kernel),
-   then one sweep of the smoother on the finest level of the 3D Q4 128^3
-   workload (8 color steps: one kernel each for the combined form, a residual
-   and a solve kernel each for the separated form).
+   then one sweep of the smoother on one 3D level (default: the finest level
+   of the 3D Q4 128^3 workload; ``--degree``, ``--cells`` pick another):
+   8 color steps, one kernel each for the combined form, a residual and a
+   solve kernel each for the separated form.
 2. ``python -m paper_2407_02100_amd.traffic_probe summarize FETCH_CSV WRITE_CSV [--out FILE]``
    reads the two counter files (FETCH_SIZE and WRITE_SIZE passes, in KiB per
    dispatch), scales each counter by the value it reads for the copy kernel
@@ -128,6 +129,8 @@ if __name__ == "__main__":
     r.add_argument("--algorithm", default="combined")
     r.add_argument("--order", type=int, default=0, help="vps_config.patch_order")
     r.add_argument("--batch-layers", type=int, default=0, help="vps_config.batch_layers")
+    r.add_argument("--degree", type=int, default=4, help="Q_k degree of the 3D level swept")
+    r.add_argument("--cells", type=int, default=128, help="cells per direction of the 3D level swept")
     s = sub.add_parser("summarize")
     s.add_argument("fetch_csv")
     s.add_argument("write_csv")
@@ -136,6 +139,7 @@ if __name__ == "__main__":
     s.add_argument("--batch-layers", type=int, default=0, help="the batch_layers the counters were taken with")
     a = ap.parse_args()
     if a.cmd == "run":
-        run(a.dtype, algorithm=a.algorithm, order=a.order, batch_layers=a.batch_layers)
+        run(a.dtype, n_cells=a.cells, degree=a.degree, algorithm=a.algorithm, order=a.order,
+            batch_layers=a.batch_layers)
     else:
         summarize(a.fetch_csv, a.write_csv, a.dtype, out_path=a.out, batch_layers=a.batch_layers)
