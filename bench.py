@@ -94,12 +94,12 @@ def finest_smoother_kernel(dim: int, k: int, n_cells: int, vcycle: str, coef: st
         return "patch_color_kernel"
     if dim == 2:
         return "patch_row2_kernel" if n_cells >= 64 and k >= 2 else "patch_color_kernel"
-    if k == 5:
-        return "patch_big3_kernel"
     if k == 1:
         return "patch_color_kernel"
     if (k == 2 and n_cells >= 32) or (k >= 3 and n_cells >= 64):
-        return "patch_row3_kernel"
+        return "patch_row5_kernel" if k == 5 else "patch_row3_kernel"
+    if k == 5:
+        return "patch_big3_kernel"
     if n_cells >= 32 and not (vcycle == "f32" and k == 4):
         return "patch_pair3_kernel"
     return "patch_wave3_kernel"

@@ -368,6 +368,11 @@ bool pair_kernel_applies(const vps_config& C) {
   return C.dim == 3 && C.coef == VPS_COEF_CONST && C.degree >= 2 && C.degree <= 4 &&
          C.algorithm == VPS_ALG_COMBINED && C.patch_order == 0 && C.patches_per_block == 0;
 }
+// the row-of-patches smoother kernels: as the pair kernel, degrees 2..5 (degree 5: two waves per row)
+bool row_kernel_applies(const vps_config& C) {
+  return C.dim == 3 && C.coef == VPS_COEF_CONST && C.degree >= 2 && C.degree <= 5 &&
+         C.algorithm == VPS_ALG_COMBINED && C.patch_order == 0 && C.patches_per_block == 0;
+}
 
 int stream_min(const vps_context* c) {
   if (c->cfg.dim == 3 && c->cfg.degree == 5) return 1;  // the single-pass 3D tiles exceed the LDS at k = 5
@@ -400,15 +405,16 @@ hipError_t do_smooth_color(vps_context* c, int l, void* u, const void* b, vps_dt
   P.pb = c->cfg.patches_per_block;  // 0: the launcher chooses
   P.order = c->cfg.patch_order;
   // automatic (sweeps measured per degree, precision and level size): a row of
-  // patches per wave at degree 2 from 32 cells per direction, at degrees 3 and 4
-  // from 64; otherwise pairs from 32 cells except FP32 at degree 4; one patch per
-  // wave on smaller levels (too few groups to fill the chip)
+  // patches per wave (degree 5: per workgroup of two waves) at degree 2 from 32
+  // cells per direction, at degrees 3 to 5 from 64; otherwise pairs from 32 cells
+  // except FP32 at degree 4 and at degree 5 (no pair kernel); one patch per wave
+  // on smaller levels (too few groups to fill the chip)
   const int deg = c->cfg.degree;
   const bool row_auto = (deg == 2 && L.ncell >= 32) || (deg >= 3 && L.ncell >= 64);
-  const bool pair_auto = L.ncell >= 32 && !(t == VPS_F32 && deg == 4);
+  const bool pair_auto = L.ncell >= 32 && !(t == VPS_F32 && deg == 4) && deg <= 4;
   int ppw = c->cfg.patches_per_wave;
   if (ppw == 0) ppw = row_auto ? 3 : (pair_auto ? 2 : 1);
-  P.ppw = pair_kernel_applies(c->cfg) ? ppw : 1;
+  P.ppw = (ppw == 3 ? row_kernel_applies(c->cfg) : pair_kernel_applies(c->cfg)) ? ppw : 1;
   P.row2 = c->cfg.wave_rows_2d;
   P.vlo = vlo;
   P.vhi = vhi;
@@ -796,7 +802,8 @@ vps_status vps_create(const vps_config* cfg, void* hip_stream, vps_context** out
   if (C.batch_layers < 0) return VPS_E_ARG;
   if (C.batch_layers > 0 && C.algorithm != VPS_ALG_COMBINED) return VPS_E_UNSUPPORTED;
   if (C.patches_per_wave < 0 || C.patches_per_wave > 3) return VPS_E_ARG;
-  if (C.patches_per_wave >= 2 && !pair_kernel_applies(C)) return VPS_E_UNSUPPORTED;
+  if (C.patches_per_wave == 2 && !pair_kernel_applies(C)) return VPS_E_UNSUPPORTED;
+  if (C.patches_per_wave == 3 && !row_kernel_applies(C)) return VPS_E_UNSUPPORTED;
   if (C.vcycle_graph != 0 && C.vcycle_graph != 1) return VPS_E_ARG;
   if (C.wave_rows_2d < 0 || C.wave_rows_2d > 2) return VPS_E_ARG;
   if (C.wave_rows_2d == 1 && (C.dim != 2 || C.coef != VPS_COEF_CONST || C.degree < 2 || C.patches_per_block != 0))

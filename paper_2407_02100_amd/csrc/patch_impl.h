@@ -7,6 +7,7 @@
 #include "patch_pair.h"
 #include "patch_row2.h"
 #include "patch_row3.h"
+#include "patch_row5.h"
 #include "patch_big.h"
 #include "patch_solve.h"
 #include "launch.h"
@@ -35,6 +36,43 @@ hipError_t go_patch_pb(const PatchArgs<T, K>& a, int pb, hipStream_t s) {
     case 4: return go_patch<T, K, D, COEF, 4>(a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Arguments of the row kernels (groups of G patches of one color, packed along
+// the rows of patches when a row holds at least G of them); false if the
+// group decomposition's exact divisions do not hold.
+template <typename T, int K, int G>
+bool fill_row_args(const PatchArgs<T, K>& a, const PatchLaunch& L, unsigned vec_bytes, Row3Args<T, K>* w) {
+  w->u = a.u;
+  w->b = a.b;
+  w->n1 = a.n1;
+  for (int e = 0; e < 3; ++e) {
+    w->v0[e] = a.v0[e];
+    w->np[e] = a.np[e];
+  }
+  w->ngx = (a.np[0] + G - 1) / G;
+  const unsigned long long npatch = (unsigned long long)a.np[0] * (unsigned)a.np[1] * (unsigned)a.np[2];
+  w->packed = a.np[0] >= G ? 1 : 0;
+  const unsigned long long ng = w->packed ? (npatch + G - 1) / G
+                                          : (unsigned long long)w->ngx * (unsigned)a.np[1] * (unsigned)a.np[2];
+  // the group decomposition divides numbers below ngroups by ngx and np[1] (row groups) or
+  // numbers below npatch by np[0] and np[1] (packed)
+  if (ng * (unsigned)w->ngx >= (1ull << 32) || ng * (unsigned)a.np[1] >= (1ull << 32) ||
+      npatch * (unsigned)a.np[0] >= (1ull << 32) || npatch * (unsigned)a.np[1] >= (1ull << 32))
+    return false;
+  w->ngroups = (unsigned)ng;
+  w->npatch = (unsigned)npatch;
+  w->vec_bytes = vec_bytes;
+  w->magic_g = magic_of((unsigned)w->ngx);
+  w->magic_x = magic_of((unsigned)a.np[0]);
+  w->magic_y = magic_of((unsigned)a.np[1]);
+  PatchBand<T, K> band;
+  if (!make_band<T, K>(L.M[0], L.Kst[0], &band)) return false;
+  make_sym_band<T, K>(band, &w->band);
+  for (int i = 0; i < K * K; ++i) w->f.Te[i] = (T)L.Te[i];
+  for (int i = 0; i < (K - 1) * (K - 1); ++i) w->f.To[i] = (T)L.To[i];
+  for (int i = 0; i < 2 * K - 1; ++i) w->lam[i] = (T)L.lam_int[i];
+  return true;
 }
 
 }  // namespace
@@ -105,7 +143,18 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
     }
   }
   if (D == 3 && L.coef == 0 && L.pb == 0 && L.order == 0 && L.Te && L.lam_int) {
-    if constexpr (K == 5) {  // one patch per wave, the interior lines in passes of 64
+    if constexpr (K == 5) {
+      if (L.ppw == 3) {  // a row of patches per workgroup of two waves
+        static_assert(sizeof(Row3Args<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
+        const unsigned long long vbytes = (unsigned long long)a.n1 * a.n1 * a.n1 * sizeof(T);
+        if (vbytes >= (1ull << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
+        Row3Args<T, K> w;
+        if (!fill_row_args<T, K, Row5Shape<K>::G>(a, L, (unsigned)vbytes, &w)) return hipErrorInvalidValue;
+        const unsigned grid = (w.ngroups + kXcd - 1) / kXcd * kXcd;  // a multiple of the XCD count
+        patch_row5_kernel<T, K><<<grid, 128, 0, s>>>(w);
+        return hipGetLastError();
+      }
+      // one patch per wave, the interior lines in passes of 64
       static_assert(sizeof(BigArgs<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
       BigArgs<T, K> w;
       w.u = a.u;
@@ -144,39 +193,8 @@ hipError_t launch_patch_color(const PatchLaunch& L, hipStream_t s) {
       if (L.ppw == 3) {
         if (L.order != 0) return hipErrorInvalidValue;  // rows are visited in lexicographic order only
         static_assert(sizeof(Row3Args<T, K>) <= 4096, "kernel arguments exceed 4 KiB");
-        using R = Row3Shape<K>;
         Row3Args<T, K> w;
-        w.u = a.u;
-        w.b = a.b;
-        w.n1 = a.n1;
-        for (int e = 0; e < 3; ++e) {
-          w.v0[e] = a.v0[e];
-          w.np[e] = a.np[e];
-        }
-        w.ngx = (a.np[0] + R::G - 1) / R::G;
-        const unsigned long long npatch = (unsigned long long)a.np[0] * (unsigned)a.np[1] * (unsigned)a.np[2];
-        // packed groups (every group but the last holds G patches, a group may continue on the
-        // next row of patches) when a row holds at least G patches, row groups otherwise
-        w.packed = a.np[0] >= R::G ? 1 : 0;
-        const unsigned long long ng = w.packed ? (npatch + R::G - 1) / R::G
-                                               : (unsigned long long)w.ngx * (unsigned)a.np[1] * (unsigned)a.np[2];
-        // the group decomposition divides numbers below ngroups by ngx and np[1] (row groups) or
-        // numbers below npatch by np[0] and np[1] (packed)
-        if (ng * (unsigned)w.ngx >= (1ull << 32) || ng * (unsigned)a.np[1] >= (1ull << 32) ||
-            npatch * (unsigned)a.np[0] >= (1ull << 32) || npatch * (unsigned)a.np[1] >= (1ull << 32))
-          return hipErrorInvalidValue;
-        w.ngroups = (unsigned)ng;
-        w.npatch = (unsigned)npatch;
-        w.vec_bytes = (unsigned)vbytes;
-        w.magic_g = magic_of((unsigned)w.ngx);
-        w.magic_x = magic_of((unsigned)a.np[0]);
-        w.magic_y = magic_of((unsigned)a.np[1]);
-        PatchBand<T, K> band;
-        if (!make_band<T, K>(L.M[0], L.Kst[0], &band)) return hipErrorInvalidValue;
-        make_sym_band<T, K>(band, &w.band);
-        for (int i = 0; i < K * K; ++i) w.f.Te[i] = (T)L.Te[i];
-        for (int i = 0; i < (K - 1) * (K - 1); ++i) w.f.To[i] = (T)L.To[i];
-        for (int i = 0; i < Q; ++i) w.lam[i] = (T)L.lam_int[i];
+        if (!fill_row_args<T, K, Row3Shape<K>::G>(a, L, (unsigned)vbytes, &w)) return hipErrorInvalidValue;
         const unsigned grid = (w.ngroups + kXcd - 1) / kXcd * kXcd;  // a multiple of the XCD count
         patch_row3_kernel<T, K><<<grid, 64, 0, s>>>(w);
         return hipGetLastError();

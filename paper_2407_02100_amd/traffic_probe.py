@@ -45,7 +45,7 @@ def kernel_source_hash() -> str:
 
 
 def run(dtype: str, n_cells: int = 128, degree: int = 4, algorithm: str = "combined", order: int = 0,
-        batch_layers: int = 0):
+        batch_layers: int = 0, patches_per_wave: int = 0):
     if ROOT not in sys.path:
         sys.path.insert(0, ROOT)
     import torch
@@ -60,7 +60,7 @@ def run(dtype: str, n_cells: int = 128, degree: int = 4, algorithm: str = "combi
     b = torch.from_numpy(vi.seeded_vector(3, degree, n_cells, 5)).to("cuda", tdt)
     u = torch.from_numpy(vi.seeded_vector(3, degree, n_cells, 105)).to("cuda", tdt)
     with vps.Context(3, degree, n_cells, 1, vcycle_dtype=dtype, algorithm=algorithm, patch_order=order,
-                     batch_layers=batch_layers) as ctx:
+                     batch_layers=batch_layers, patches_per_wave=patches_per_wave) as ctx:
         ctx.smooth(0, u, b, sweeps=1)
         ctx.sync()
     print("traffic probe done", flush=True)
@@ -78,8 +78,8 @@ def _read(path):
     return out
 
 
-SMOOTHER_KERNELS = ("patch_wave3_kernel", "patch_pair3_kernel", "patch_row3_kernel", "patch_color_kernel",
-                    "patch_solve3_kernel", "stream3_kernel")
+SMOOTHER_KERNELS = ("patch_wave3_kernel", "patch_pair3_kernel", "patch_row3_kernel", "patch_row5_kernel",
+                    "patch_big3_kernel", "patch_color_kernel", "patch_solve3_kernel", "stream3_kernel")
 
 
 def summarize(fetch_csv: str, write_csv: str, dtype: str, workload: str = "poisson3d_q4_n128",
@@ -110,8 +110,9 @@ def summarize(fetch_csv: str, write_csv: str, dtype: str, workload: str = "poiss
            "kernels": kernels, "bytes_per_sweep": sweep, "calibration": scales,
            "note": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE per dispatch, each scaled by the value the "
                    "same counter reads for a plain copy of 512 MiB in the same process"}
-    main = (kernels.get("patch_row3_kernel") or kernels.get("patch_wave3_kernel") or kernels.get("patch_pair3_kernel")
-            or kernels.get("patch_color_kernel"))
+    main = next((kernels[k] for k in ("patch_row3_kernel", "patch_row5_kernel", "patch_big3_kernel",
+                                      "patch_wave3_kernel", "patch_pair3_kernel", "patch_color_kernel")
+                 if k in kernels), None)
     if main:
         doc["bytes_per_launch"] = main["fetch_bytes_per_launch"] + main["write_bytes_per_launch"]
     out_path = out_path or os.path.join(ROOT, "profiles", "patch_sweep_traffic.json")
@@ -131,6 +132,7 @@ if __name__ == "__main__":
     r.add_argument("--batch-layers", type=int, default=0, help="vps_config.batch_layers")
     r.add_argument("--degree", type=int, default=4, help="Q_k degree of the 3D level swept")
     r.add_argument("--cells", type=int, default=128, help="cells per direction of the 3D level swept")
+    r.add_argument("--ppw", type=int, default=0, help="vps_config.patches_per_wave")
     s = sub.add_parser("summarize")
     s.add_argument("fetch_csv")
     s.add_argument("write_csv")
@@ -140,6 +142,6 @@ if __name__ == "__main__":
     a = ap.parse_args()
     if a.cmd == "run":
         run(a.dtype, n_cells=a.cells, degree=a.degree, algorithm=a.algorithm, order=a.order,
-            batch_layers=a.batch_layers)
+            batch_layers=a.batch_layers, patches_per_wave=a.ppw)
     else:
         summarize(a.fetch_csv, a.write_csv, a.dtype, out_path=a.out, batch_layers=a.batch_layers)

@@ -73,7 +73,8 @@ def test_status_strings(lib):
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=2, algorithm=1), -2),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, patches_per_wave=2, patches_per_block=2), -2),
     (dict(dim=2, degree=2, n_cells=8, n_levels=2, patches_per_wave=3), -2),   # rows of patches: 3D only
-    (dict(dim=3, degree=5, n_cells=8, n_levels=2, patches_per_wave=3), -2),   # rows of patches: degree 2..4
+    (dict(dim=3, degree=1, n_cells=8, n_levels=2, patches_per_wave=3), -2),   # rows of patches: degree 2..5
+    (dict(dim=3, degree=5, n_cells=8, n_levels=2, patches_per_wave=3, patch_order=1), -2),
     (dict(dim=3, degree=3, n_cells=8, n_levels=2, patches_per_wave=3, patch_order=3), -2),
     (dict(dim=3, degree=2, n_cells=8, n_levels=2, coef=4), -1),
     (dict(dim=2, degree=2, n_cells=8, n_levels=2, coef=3), -2),   # exact local solvers: Q2 in 3D only

@@ -84,7 +84,8 @@ def test_sweep_bytes_of_the_513_workload():
     (3, 4, 128, "f32", "const", "patch_row3_kernel"), (3, 4, 64, "f64", "const", "patch_row3_kernel"),
     (3, 4, 32, "f32", "const", "patch_wave3_kernel"), (3, 4, 32, "f64", "const", "patch_pair3_kernel"),
     (3, 3, 32, "f32", "const", "patch_pair3_kernel"), (3, 2, 32, "f64", "const", "patch_row3_kernel"),
-    (3, 2, 16, "f64", "const", "patch_wave3_kernel"), (3, 5, 128, "f64", "const", "patch_big3_kernel"),
+    (3, 2, 16, "f64", "const", "patch_wave3_kernel"), (3, 5, 128, "f64", "const", "patch_row5_kernel"),
+    (3, 5, 32, "f64", "const", "patch_big3_kernel"), (3, 5, 64, "f32", "const", "patch_row5_kernel"),
     (2, 3, 2048, "f64", "const", "patch_row2_kernel"), (3, 2, 64, "f64", "learned", "patch_color_kernel")])
 def test_finest_smoother_kernel_follows_the_automatic_choice(dim, k, n, vcycle, coef, want):
     assert bench.finest_smoother_kernel(dim, k, n, vcycle, coef) == want

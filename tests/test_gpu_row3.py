@@ -1,7 +1,8 @@
 """GPU parity of the 3D smoother kernel that takes a row of x-adjacent patches of a color per wavefront.
 
 G = floor(63 / 2k) patches side by side (15, 10, 7 for k = 2, 3, 4) span G*2k + 1
-node columns, one lane per column.  Sizes give colors with full and ragged last
+node columns, one lane per column; at k = 5 a workgroup of two waves takes G = 5
+patches (51 or 52 columns).  Sizes give colors with full and ragged last
 groups along x, several groups per color row, single-patch rows and the
 single-patch domain; the update is the same exact local solve as with one
 patch per wavefront.
@@ -15,8 +16,10 @@ from tests.gpu_util import dev, host, rel, say
 
 pytestmark = pytest.mark.gpu
 
-# (k, N): colors have (N - 1) // 2 or N // 2 patches along x against groups of 15 / 10 / 7
-ROW3_CASES = [(2, 32), (3, 22), (4, 18), (4, 9), (2, 5), (3, 4), (4, 3), (4, 2)]
+# (k, N): colors have (N - 1) // 2 or N // 2 patches along x against groups of 15 / 10 / 7 / 5
+# (degree 5: a workgroup of two waves per group); packed groups from G patches per row on
+ROW3_CASES = [(2, 32), (3, 22), (4, 18), (4, 9), (2, 5), (3, 4), (4, 3), (4, 2),
+              (5, 14), (5, 12), (5, 11), (5, 8), (5, 3), (5, 2)]
 
 
 @pytest.fixture(scope="module")
@@ -43,7 +46,7 @@ def test_row3_colors_fp64(vps, k, N):
             assert rel(host(u), uo) <= 1e-12, (c, rel(host(u), uo))
 
 
-@pytest.mark.parametrize("k,N", [(2, 32), (3, 22), (4, 18), (4, 6)])
+@pytest.mark.parametrize("k,N", [(2, 32), (3, 22), (4, 18), (4, 6), (5, 14), (5, 7)])
 @pytest.mark.parametrize("reverse", [False, True])
 def test_row3_sweep_fp32(vps, k, N, reverse):
     """FP32 sweeps with rows of patches: against the oracle (FP32 rounding) and against one patch per wavefront."""
@@ -65,11 +68,11 @@ def test_row3_sweep_fp32(vps, k, N, reverse):
     assert rel(out[3], out[1]) <= 2e-5
 
 
-def test_row3_batched_fp32_matches_whole_colors(vps):
+@pytest.mark.parametrize("k,N", [(4, 10), (5, 8)])
+def test_row3_batched_fp32_matches_whole_colors(vps, k, N):
     """Slabs of 2 vertex layers (even: Algorithm 4's iterate) with rows of patches, FP32, against the oracle."""
     import torch
-    k, N = 4, 10
-    say("row3 batched fp32")
+    say("row3 batched fp32", k, N)
     b = vi.seeded_vector(3, k, N, 177).astype(np.float32).astype(np.float64)
     u0 = vi.seeded_vector(3, k, N, 178).astype(np.float32).astype(np.float64)
     out = {}
