@@ -314,10 +314,14 @@ def run_paper_workloads(torch, vps, vi):
             ctx.solve(b, x, rtol=1e-12, maxit=100)
             info = ctx.solve(b, x, rtol=1e-12, maxit=100)
         n = b.numel()
+        byt = sweep_bytes(dim, k, N, 8, 0)  # algorithmic bytes of one FP64 sweep on whole colors
         out[name] = {"nodes": n, "smoothing_s": sweep_ms * 1e-3, "vmult_s": vmult_ms * 1e-3,
                      "iterations": info["iterations"], "solve_s": info["seconds"],
                      "rel_residual_true": info["rel_residual_true"],
-                     "smoother_dof_per_s": n / (sweep_ms * 1e-3), "paper_cpu_32_cores": paper}
+                     "smoother_dof_per_s": n / (sweep_ms * 1e-3),
+                     "smoother_kernel": finest_smoother_kernel(dim, k, N, "f64", "const"),
+                     "smoother_alg_bytes_per_sweep": byt, "smoother_frac_of_8tbs": byt / (sweep_ms * 1e-3) / 8e12,
+                     "paper_cpu_32_cores": paper}
         del b, u, x, Au
     return out
 
