@@ -6,11 +6,15 @@
   untouched; the residual vanishes on the color's interiors afterwards
   (exact local solves); the mixed-precision solve's true residual is
   recomputed on the host with the oracle's Kronecker-form product.
+* The paper's 3D Q5 shape, 128^3 cells (641^3 nodes): one color on sampled
+  patches as above, one patch per wave and a row of five per workgroup.
 * 3D Q3 on 64^3 cells: plain FP64 and FP32-preconditioned solves, rechecked on
   the host, same solution.
 * 3D Q2 on 64^3 cells with rho = exp(GRF): plain rhobar-FDM and learned
   scaling, rechecked on the host with the oracle's cell-by-cell product.
 """
+import functools
+
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -98,6 +102,45 @@ def test_color_on_sampled_patches_full_size(vps, dtype, color, ppw):
         want = sla.cho_solve(cho, b[inner] - Aig @ u0[clo[gpos]])
         got = u1[inner]
         assert np.abs(got - want).max() <= tol * np.abs(want).max(), v
+
+
+@functools.lru_cache(maxsize=1)
+def _q5_inputs():
+    return vi.seeded_vector(3, 5, 128, 113), vi.seeded_vector(3, 5, 128, 13)
+
+
+@pytest.mark.parametrize("dtype,color", [("f64", 3), ("f64", 6), ("f32", 5)])
+@pytest.mark.parametrize("ppw", [1, 3])
+def test_color_on_sampled_patches_paper_q5_shape(vps, dtype, color, ppw):
+    """The paper's 3D Q5 shape, 128^3 cells (641^3 nodes): one color launch (one patch per wave, or a row of
+    five patches per workgroup of two waves, the automatic choice there) against the oracle's exact local
+    solve of sampled patches; cond(A_j) is about 68 at k = 5."""
+    import torch
+    k, N = 5, 128
+    say("paper Q5 shape color", dtype, color, ppw)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    u0, b = _q5_inputs()
+    if dtype == "f32":
+        u0 = u0.astype(np.float32).astype(np.float64)
+        b = b.astype(np.float32).astype(np.float64)
+    with vps.Context(3, k, N, 1, vcycle_dtype=dtype, patches_per_wave=ppw) as ctx:
+        u = dev(u0, tdt)
+        ctx.smooth_color(0, u, dev(b, tdt), color)
+        u1 = host(u)
+        del u
+    mask = _color_interior_mask(3, k, N, color)
+    assert np.array_equal(u1[~mask], u0[~mask])
+    Abar = smoother.patch_closure_operator(3, k, 1.0 / N)
+    ipos = smoother.closure_interior_positions(3, k)
+    gpos = np.setdiff1d(np.arange(Abar.shape[0]), ipos)
+    cho = sla.cho_factor(Abar[np.ix_(ipos, ipos)])
+    Aig = Abar[np.ix_(ipos, gpos)]
+    tol = 5e-5 if dtype == "f32" else 1e-11
+    for v in _sample_vertices(N, color, 40, 31 + color):
+        clo = mesh.patch_closure(3, k, N, v)
+        inner = clo[ipos]
+        want = sla.cho_solve(cho, b[inner] - Aig @ u0[clo[gpos]])
+        assert np.abs(u1[inner] - want).max() <= tol * np.abs(want).max(), v
 
 
 def test_residual_vanishes_on_color_interiors_full_size(vps):
