@@ -117,16 +117,19 @@ typedef struct {
                             backwards); smaller levels sweep whole colors.  Even B visits
                             every pair of interacting patches in the colorized order, i.e.
                             gives Algorithm 4's iterate.  Combined algorithm only; >= 0 */
-  int patches_per_wave;  /* 3D, rho = 1, degree 2..4, combined algorithm, patch_order 0:
-                            patches of a color per wavefront in the smoother: 1 = one
-                            patch; 2 = two x-adjacent patches that share a closure face
-                            (their boundary columns are loaded together); 3 = a row of
+  int patches_per_wave;  /* 3D, rho = 1, combined algorithm, patch_order 0: patches of a
+                            color per wavefront in the smoother: 1 = one patch; 2 = two
+                            x-adjacent patches that share a closure face (their boundary
+                            columns are loaded together; degree 2..4); 3 = a row of
                             floor(63 / 2k) x-adjacent patches (lanes on node columns,
-                            closure rows loaded as contiguous runs); 0 = automatic
-                            (3 at degree 2 from 32 cells per direction, at degrees 3
-                            and 4 from 64; else 2 from 32 cells except FP32 at
-                            degree 4; 1 otherwise).  Same update either way,
-                            different rounding order */
+                            closure rows loaded as contiguous runs; degree 2..4), at
+                            degree 5 a row of 5 patches per workgroup of two wavefronts
+                            (one on the closure columns, one on the patch rows);
+                            0 = automatic (3 at degree 2 from 32 cells per direction,
+                            at degrees 3 to 5 from 64; else 2 from 32 cells except
+                            FP32 at degree 4 and at degree 5; 1 otherwise).
+                            VPS_E_UNSUPPORTED for 2 or 3 outside these cases.  Same
+                            update either way, different rounding order */
   int vcycle_graph;      /* 1: the finest-level V-cycle of vps_vcycle and vps_solve is
                             captured once per (input, output) buffer pair into a HIP
                             graph on a stream of the library's own and replayed on the

@@ -31,16 +31,44 @@ ROOT = os.path.dirname(HERE)
 COPY_BYTES = 512 * 1024 * 1024  # bytes read by the calibration copy (and written)
 
 
+def strip_comments(src: str) -> str:
+    """C/C++ source without its comments (string and character literals kept), each comment
+    replaced by one space: what the compiler sees."""
+    out = []
+    i, n = 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+            out.append(" ")
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return "".join(out)
+
+
 def kernel_source_hash() -> str:
-    """Hash of every library source (kernels, launchers, host driver) and the C header: a traffic
-    profile taken with other sources is void, whichever file changed the kernel or its launch."""
+    """Hash of every library source (kernels, launchers, host driver) and the C header, comments
+    left out: a traffic profile taken with other code is void, whichever file changed the kernel or
+    its launch; a change to the comments alone keeps it."""
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
     files = sorted(f for f in os.listdir(csrc) if f.endswith((".h", ".hip", ".cpp")))
     for f in files + [os.path.join("..", "..", "include", "vps.h")]:
         h.update(f.encode())
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update(strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -106,3 +106,24 @@ def test_median_helper_handles_one_and_three_runs():
     assert out == 1 and len(calls) == 1 and t >= 0.0
     t, out = bench._median3(lambda: calls.append(1) or len(calls))
     assert out == 4 and len(calls) == 4
+
+
+def test_source_hash_ignores_comments_only():
+    from paper_2407_02100_amd import traffic_probe as tp
+    src = 'int a = 1; // x\n/* y */ const char* s = "// kept /* kept */"; char q = \'"\'; /* z\n w */ int b;\n'
+    out = tp.strip_comments(src)
+    assert "// kept /* kept */" in out and "x" not in out.replace("// kept", "") and "int b;" in out
+    assert out.count("\n") == 2  # a block comment's newlines go with it; a line comment keeps its newline
+    assert tp.strip_comments("a /* c */ b") == "a   b"
+
+
+def test_committed_traffic_profiles_match_the_sources():
+    """The committed FETCH/WRITE summaries were taken with the current kernel code (else the bench line's
+    roofline.traffic is null)."""
+    import json
+    from paper_2407_02100_amd import traffic_probe as tp
+    for name, dtype, bl in (("patch_sweep_traffic.json", "f32", 44), ("patch_sweep_traffic_f64.json", "f64", 0)):
+        path = os.path.join(ROOT, "profiles", name)
+        doc = json.load(open(path))
+        assert doc["kernel_source_hash"] == tp.kernel_source_hash(), name
+        assert bench.traffic_per_launch(path, "poisson3d_q4_n128", bl, dtype) == doc["bytes_per_launch"]
