@@ -38,7 +38,7 @@ def brute_counts(dim, k, n, vlo=1, vhi=None):
 
 
 @pytest.mark.parametrize("dim,k,n", [(2, 1, 6), (2, 2, 6), (2, 3, 5), (2, 5, 4), (3, 1, 5), (3, 2, 4), (3, 4, 3),
-                                     (3, 3, 6)])
+                                     (3, 3, 6), (3, 5, 3), (3, 5, 5)])
 def test_color_counts_match_brute_force(dim, k, n):
     assert bench.color_counts(dim, k, n) == brute_counts(dim, k, n)
 
@@ -78,6 +78,15 @@ def test_sweep_bytes_of_the_513_workload():
     counts = bench.color_counts(3, 4, 128)
     assert 0.95 * n < sum(c for c, _ in counts) / 8 <= n
     assert abs(sum(i for _, i in counts) / 8 / n - (7 / 8) ** 3) < 0.02
+
+
+def test_sweep_bytes_of_the_paper_q5_shape():
+    """The algorithmic bytes of one FP64 sweep of the paper's 3D Q5 128^3 shape (641^3 nodes), whole colors."""
+    byt = bench.sweep_bytes(3, 5, 128, 8)
+    assert byt == sum((c + 2 * i) * 8 for c, i in bench.color_counts(3, 5, 128))
+    assert byt == 40_356_944_496
+    n = 641 ** 3
+    assert 8 * n * 8 * 0.95 < byt - 2 * 8 * sum(i for _, i in bench.color_counts(3, 5, 128)) <= 8 * n * 8
 
 
 @pytest.mark.parametrize("dim,k,n,vcycle,coef,want", [
