@@ -34,6 +34,23 @@ def test_batched_sweep_odd_layers(vps, dim, k, N, B, reverse):
         assert rel(host(u), want) <= 1e-12
 
 
+@pytest.mark.parametrize("k,N,B", [(4, 10, 3), (5, 8, 3), (5, 9, 1)])
+def test_batched_sweep_odd_layers_rows(vps, k, N, B):
+    """Odd batch sizes with rows of patches (degree 5: two waves per row), FP64, against the oracle's
+    batched sweep."""
+    say("batched sweep rows", k, N, B)
+    A = assemble.assemble(3, k, N)
+    P = smoother.Patches(3, k, N)
+    S = smoother.LocalSolvers(A, P, "shared")
+    b = vi.seeded_vector(3, k, N, 93)
+    u0 = vi.seeded_vector(3, k, N, 94)
+    want = smoother.sweep_batched(A, b, u0, P, S, B, False)
+    with vps.Context(3, k, N, 1, batch_layers=B, patches_per_wave=3) as ctx:
+        u = dev(u0)
+        ctx.smooth(0, u, dev(b), sweeps=1)
+        assert rel(host(u), want) <= 1e-12
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("B", [2, 4, 8])
 def test_batched_even_layers_bitwise(vps, dtype, B):
