@@ -48,6 +48,10 @@ def test_gll_closed_forms():
     s = np.sqrt(3.0 / 7.0)
     assert np.allclose(x4, [0.0, 0.5 * (1 - s), 0.5, 0.5 * (1 + s), 1.0], atol=1e-15)
     assert np.allclose(fe.gll_nodes(2), [0.0, 0.5, 1.0], atol=1e-15)
+    # k = 5: the interior nodes are the roots of P_5', 21 x^4 - 14 x^2 + 1 = 0 on [-1, 1]
+    a5, b5 = np.sqrt(1.0 / 3.0 - 2.0 * np.sqrt(7.0) / 21.0), np.sqrt(1.0 / 3.0 + 2.0 * np.sqrt(7.0) / 21.0)
+    want = 0.5 * (1.0 + np.array([-1.0, -b5, -a5, a5, b5, 1.0]))
+    assert np.allclose(fe.gll_nodes(5), want, atol=1e-15)
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
