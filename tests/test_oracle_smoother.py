@@ -16,7 +16,7 @@ def _setup(dim, k, N, mode="exact", rho=None):
     return A, P, S
 
 
-@pytest.mark.parametrize("dim,k,N", [(2, 1, 4), (2, 2, 4), (2, 4, 4), (3, 2, 4), (3, 3, 3)])
+@pytest.mark.parametrize("dim,k,N", [(2, 1, 4), (2, 2, 4), (2, 4, 4), (3, 2, 4), (3, 3, 3), (2, 5, 3), (3, 5, 2)])
 def test_patch_block_is_kronecker_sum(dim, k, N):
     """A[I_j, I_j] equals the Kronecker sum of the 1D patch matrices (Appendix A.3) for every patch."""
     A = assemble.assemble(dim, k, N)
@@ -26,7 +26,7 @@ def test_patch_block_is_kronecker_sum(dim, k, N):
         assert np.abs(A[I][:, I].toarray() - Ab).max() < 1e-13 * np.abs(Ab).max()
 
 
-@pytest.mark.parametrize("dim,k", [(2, 2), (2, 4), (3, 2), (3, 4)])
+@pytest.mark.parametrize("dim,k", [(2, 2), (2, 4), (3, 2), (3, 4), (2, 5), (3, 5)])
 def test_fdm_inverse_equals_dense_solve(dim, k):
     h = 1.0 / 16
     S, Lam, T, lam = smoother.fdm_factors(dim, k, h)
@@ -39,7 +39,7 @@ def test_fdm_inverse_equals_dense_solve(dim, k):
     assert np.allclose(T.T @ Mj @ T, np.eye(T.shape[0]), atol=1e-12)
 
 
-@pytest.mark.parametrize("dim,k", [(2, 2), (2, 3), (3, 2)])
+@pytest.mark.parametrize("dim,k", [(2, 2), (2, 3), (3, 2), (2, 5), (3, 5)])
 def test_single_patch_sweep_is_exact_solve(dim, k):
     """N = 2: the only patch covers all free nodes, so one sweep solves A u = b."""
     A, P, S = _setup(dim, k, 2)
