@@ -7,7 +7,7 @@ from oracle import multigrid, manufactured, mesh
 
 
 @pytest.mark.parametrize("dim,k,Ns", [(2, 1, (4, 8, 16)), (2, 2, (4, 8, 16)), (2, 3, (4, 8)), (2, 4, (4, 8)),
-                                     (3, 2, (4, 8))])
+                                     (2, 5, (4, 8)), (3, 2, (4, 8)), (3, 3, (4, 8)), (3, 5, (4, 8))])
 def test_manufactured_convergence_rate(dim, k, Ns):
     """L2 error ratio under refinement tends to 2^(k+1)."""
     errs = []
